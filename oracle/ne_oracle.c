@@ -1,0 +1,416 @@
+/*
+ * ne_oracle.c -- plain CPU reference for numerical entanglement.
+ *
+ * M. A. Anam and Y. Andreopoulos, "Reliable Linear, Sesquilinear and
+ * Bijective Operations on Integer Data Streams via Numerical Entanglement",
+ * IEEE Trans. Signal Processing (arXiv 1604.04740).
+ *
+ * TEST INFRASTRUCTURE.  This file is the oracle that the GPU library is
+ * checked against.  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark load it; the product path never does.  It
+ * shares no code, header or table with the GPU library.
+ *
+ * Conventions
+ *   - A "word" is a w-bit two's-complement integer, 4 <= w <= 64, held
+ *     sign-extended in an int64_t.  Every word operation wraps modulo 2^w.
+ *   - The interim of the disentanglement is a 2w-bit integer (__int128),
+ *     wrapping modulo 2^(2w) (section III-A, Remark 1).
+ *   - S_b{a} is the paper's shift operator: a*2^b for b >= 0 (wrapping at
+ *     the container width), arithmetic right shift by -b for b < 0.
+ *   - Streams are stored stream-major: x[m*N + n] is element n of stream m.
+ *
+ * Every step follows the paper's definitions in the paper's order; loops are
+ * written out without blocking.  The only parallelism is an OpenMP loop
+ * over independent output elements of the GEMM and the convolution, which
+ * does not change any arithmetic.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <math.h>
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+/* ---------------------------------------------------------------- words */
+
+/* Reduce to a w-bit two's-complement word (sign-extend the low w bits). */
+static int64_t word(uint64_t x, int w)
+{
+    if (w >= 64)
+        return (int64_t)x;
+    uint64_t mask = (1ull << w) - 1;
+    uint64_t sign = 1ull << (w - 1);
+    x &= mask;
+    return (int64_t)((x ^ sign) - sign);
+}
+
+/* Reduce to a 2w-bit two's-complement integer. */
+static i128 word2(u128 x, int w)
+{
+    int b = 2 * w;
+    if (b >= 128)
+        return (i128)x;
+    u128 mask = (((u128)1) << b) - 1;
+    u128 sign = ((u128)1) << (b - 1);
+    x &= mask;
+    return (i128)((x ^ sign) - sign);
+}
+
+/* S_b{a} on a w-bit word. */
+static int64_t shift_w(int64_t a, int b, int w)
+{
+    if (b >= 0)
+        return word((uint64_t)a << b, w);
+    return a >> (-b); /* arithmetic: gcc defines >> on negative values */
+}
+
+/* S_b{a} on a 2w-bit interim. */
+static i128 shift_2w(i128 a, int b, int w)
+{
+    if (b >= 0)
+        return word2((u128)a << b, w);
+    return a >> (-b);
+}
+
+static int64_t add_w(int64_t a, int64_t b, int w) { return word((uint64_t)a + (uint64_t)b, w); }
+static int64_t sub_w(int64_t a, int64_t b, int w) { return word((uint64_t)a - (uint64_t)b, w); }
+static int64_t mul_w(int64_t a, int64_t b, int w) { return word((uint64_t)a * (uint64_t)b, w); }
+
+/* ------------------------------------------------------------ parameters */
+
+/*
+ * Choice of (l, k): section III-C, constraint (M-1)l + k <= w with k <= l,
+ * maximising the supported output width (M-2)l + k (for M = 3 this is the
+ * section III-A rule 2l + k <= w, maximise l + k).  The paper does not say
+ * how to break ties; among the maximisers we take the one that fills the
+ * word exactly ((M-1)l + k == w), then the larger l.  Returns 0 on success,
+ * -1 if no admissible pair exists.
+ */
+int ne_oracle_params(int M, int w, int *l_out, int *k_out)
+{
+    int best_l = -1, best_k = -1, best_obj = -1, best_tight = 0;
+    if (M < 3 || w < 2)
+        return -1;
+    for (int l = 1; l <= w; ++l) {
+        for (int k = 0; k <= l; ++k) {
+            if ((M - 1) * l + k > w)
+                continue;
+            int obj = (M - 2) * l + k;
+            int tight = ((M - 1) * l + k == w);
+            int better = obj > best_obj ||
+                         (obj == best_obj && tight > best_tight) ||
+                         (obj == best_obj && tight == best_tight && l > best_l);
+            if (better) {
+                best_obj = obj;
+                best_l = l;
+                best_k = k;
+                best_tight = tight;
+            }
+        }
+    }
+    if (best_l < 0)
+        return -1;
+    *l_out = best_l;
+    *k_out = best_k;
+    return 0;
+}
+
+/*
+ * Dynamic range of every output, section III-C: |d| <= 2^((M-3)l+k) (2^(l-1) - 1).
+ * Returned as a 2w-bit value clipped to int64 (never exceeds 2^62 for w <= 64).
+ */
+int64_t ne_oracle_range(int M, int l, int k)
+{
+    i128 D = (((i128)1) << ((M - 3) * l + k)) * ((((i128)1) << (l - 1)) - 1);
+    if (D > (i128)INT64_MAX)
+        return INT64_MAX;
+    return (int64_t)D;
+}
+
+/* ----------------------------------------------------------- entanglement */
+
+/*
+ * Entanglement, section III-C (operator E, rows are cyclic shifts of
+ * [1 0 ... 0 S_l]); for M = 3 it is the triplet of section III-A:
+ *     eps_{m,n} = c_{m,n} + S_l{ c_{(m-1) mod M, n} }.
+ * In place is allowed (eps == c): each position is read whole before it is
+ * written, as the paper stores the entangled streams in place of the inputs.
+ */
+void ne_oracle_entangle(const int64_t *c, int64_t *eps, int M, int64_t N, int w, int l)
+{
+    int64_t col[256];
+    for (int64_t n = 0; n < N; ++n) {
+        for (int m = 0; m < M; ++m)
+            col[m] = c[(int64_t)m * N + n];
+        for (int m = 0; m < M; ++m) {
+            int prev = (m + M - 1) % M;
+            eps[(int64_t)m * N + n] = add_w(col[m], shift_w(col[prev], l, w), w);
+        }
+    }
+}
+
+/*
+ * Self-entanglement of an additive constant (footnote to the M = 3 operation
+ * in section III-A): for op in {+, -} the kernel must itself be entangled,
+ * g <- S_l{g} + g, so that the operation stays a homomorphism.
+ */
+void ne_oracle_self_entangle(const int64_t *g, int64_t *g_ent, int64_t N, int w, int l)
+{
+    for (int64_t n = 0; n < N; ++n)
+        g_ent[n] = add_w(shift_w(g[n], l, w), g[n], w);
+}
+
+/* ------------------------------------------------ LSB operations (unaware) */
+
+/*
+ * Matrix product on w-bit words: C[i][j] = sum_k A[i][k] * B[k][j] (mod 2^w).
+ * A is [R][K], B is [K][Ncol], C is [R][Ncol], all row-major.  This is the
+ * "conventional" routine of section V: it is applied unchanged to the
+ * entangled streams (section III-A, delta_m = eps_m op g).
+ */
+void ne_oracle_gemm(const int64_t *A, const int64_t *B, int64_t *C,
+                    int64_t R, int64_t K, int64_t Ncol, int w)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < R; ++i) {
+        for (int64_t j = 0; j < Ncol; ++j)
+            C[i * Ncol + j] = 0;
+        for (int64_t k = 0; k < K; ++k) {
+            int64_t a = A[i * K + k];
+            for (int64_t j = 0; j < Ncol; ++j)
+                C[i * Ncol + j] = add_w(C[i * Ncol + j], mul_w(a, B[k * Ncol + j], w), w);
+        }
+    }
+}
+
+/*
+ * Circular convolution of one stream with the kernel g (section II, the
+ * "star" operator): y[n] = sum_{k=0}^{N-1} x[(n - k) mod N] * g[k] (mod 2^w).
+ * Direct O(N^2) evaluation.
+ */
+void ne_oracle_circconv(const int64_t *x, const int64_t *g, int64_t *y, int64_t N, int w)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t acc = 0;
+        for (int64_t k = 0; k < N; ++k) {
+            int64_t idx = n - k;
+            if (idx < 0)
+                idx += N;
+            acc = add_w(acc, mul_w(x[idx], g[k], w), w);
+        }
+        y[n] = acc;
+    }
+}
+
+/*
+ * Fixed (data-independent) permutation followed by element-wise scaling and
+ * addition of a constant (section II, op in {x, +, permutation}):
+ *     y[n] = scale[n] * x[perm[n]] + add[n]   (mod 2^w).
+ * scale == NULL means 1, add == NULL means 0.  For entangled streams the
+ * caller passes the self-entangled constant (ne_oracle_self_entangle).
+ */
+void ne_oracle_permute_scale(const int64_t *x, const int64_t *perm, const int64_t *scale,
+                             const int64_t *add, int64_t *y, int64_t N, int w)
+{
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t v = x[perm[n]];
+        if (scale)
+            v = mul_w(scale[n], v, w);
+        if (add)
+            v = add_w(v, add[n], w);
+        y[n] = v;
+    }
+}
+
+/* -------------------------------------------------------- disentanglement */
+
+/*
+ * Disentanglement without stream r, section III-C (generalised to M >= 3),
+ * for every position n:
+ *
+ *   d_temp = (-1)^M * sum_{m=0}^{M-2} (-1)^m S_{(M-2-m)l}{ delta_{(r+1+m) mod M, n} }
+ *                                                            (2w-bit interim)
+ *   dhat_{(r+M-1) mod M} = S_{-[2w-(M-1)l]}{ S_{2w-(M-1)l}{ d_temp } }
+ *   dhat_r               = S_{-(M-1)l}{ (-1)^M (d_temp - dhat_{(r+M-1) mod M}) }
+ *   dhat_{(r+m) mod M}   = delta_{(r+m) mod M} - S_l{ dhat_{(r+m-1) mod M} },
+ *                                                   m = 1, ..., M-2.
+ *
+ * Two readings differ from the printed text (both are forced by the
+ * algebra and agree with the M = 3 special form of section III-A):
+ *   - the printed d_temp lacks the leading (-1)^M; with it, d_temp equals
+ *     2^((M-1)l) (-1)^M d_r + d_{r-1} and the two extraction lines that
+ *     follow it are correct as printed for every M (without it they return
+ *     -d for odd M).  For M = 3 the corrected sum is exactly the section
+ *     III-A expression delta_2 - S_l{delta_1}.
+ *   - the chain runs for 1 <= m <= M-2 (printed "< M-2", which would never
+ *     produce the output of stream r+M-2).
+ * The interim is computed in 2w bits; each output keeps the low w bits.
+ * delta is [M][N]; the row of stream r is never read (it may be garbage,
+ * which is how a fail-stop loss is modelled).  dhat is [M][N].
+ */
+void ne_oracle_extract(const int64_t *delta, int64_t *dhat, int M, int64_t N,
+                       int w, int l, int r)
+{
+    int L = (M - 1) * l;
+    int sgnM = (M % 2 == 0) ? 1 : -1;
+    for (int64_t n = 0; n < N; ++n) {
+        i128 dtemp = 0;
+        for (int m = 0; m <= M - 2; ++m) {
+            int s = (r + 1 + m) % M;
+            i128 term = shift_2w((i128)delta[(int64_t)s * N + n], (M - 2 - m) * l, w);
+            if (m % 2 == 0)
+                dtemp = word2((u128)dtemp + (u128)term, w);
+            else
+                dtemp = word2((u128)dtemp - (u128)term, w);
+        }
+        if (sgnM < 0)
+            dtemp = word2((u128)0 - (u128)dtemp, w);
+
+        int rm1 = (r + M - 1) % M;
+        i128 d_rm1 = shift_2w(shift_2w(dtemp, 2 * w - L, w), -(2 * w - L), w);
+        i128 diff = word2((u128)dtemp - (u128)d_rm1, w);
+        if (sgnM < 0)
+            diff = word2((u128)0 - (u128)diff, w);
+        i128 d_r = shift_2w(diff, -L, w);
+
+        dhat[(int64_t)rm1 * N + n] = word((uint64_t)(u128)d_rm1, w);
+        dhat[(int64_t)r * N + n] = word((uint64_t)(u128)d_r, w);
+
+        i128 prev = d_r;
+        for (int m = 1; m <= M - 2; ++m) {
+            int s = (r + m) % M;
+            i128 cur = word2((u128)(i128)delta[(int64_t)s * N + n] - (u128)shift_2w(prev, l, w), w);
+            dhat[(int64_t)s * N + n] = word((uint64_t)(u128)cur, w);
+            prev = cur;
+        }
+    }
+}
+
+/*
+ * Post-computation reliability check, section III-C and the proof of the
+ * generalised detection property (appendix): with dhat extracted without
+ * stream r, position n is flagged when
+ *     delta_{r,n} - [ dhat_{r,n} + S_l{ dhat_{(r+M-1) mod M, n} } ] != 0,
+ * evaluated exactly in 2w-bit arithmetic.  flag[n] is 0 or 1; the return
+ * value is the number of flagged positions.
+ */
+int64_t ne_oracle_check(const int64_t *delta, const int64_t *dhat, uint8_t *flag,
+                        int M, int64_t N, int w, int l, int r)
+{
+    int rm1 = (r + M - 1) % M;
+    int64_t bad = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        i128 rebuilt = word2((u128)(i128)dhat[(int64_t)r * N + n] +
+                             (u128)shift_2w((i128)dhat[(int64_t)rm1 * N + n], l, w), w);
+        i128 residual = word2((u128)(i128)delta[(int64_t)r * N + n] - (u128)rebuilt, w);
+        int f = residual != 0;
+        if (flag)
+            flag[n] = (uint8_t)f;
+        bad += f;
+    }
+    return bad;
+}
+
+/*
+ * Section III-A special form for M = 3 and r = 0, kept as written there so
+ * that the general form above can be pinned against it:
+ *     d_temp = delta_2 - S_l{delta_1}
+ *     dhat_2 = S_{-2(w-l)}{ S_{2(w-l)}{ d_temp } }
+ *     dhat_0 = S_{-2l}{ -(d_temp - dhat_2) }
+ *     dhat_1 = delta_1 - S_l{ dhat_0 }
+ * and the check of the proof of the M = 3 detection property (appendix):
+ *     flag = delta_0 - [ S_l{dhat_2} + dhat_0 ] != 0.
+ */
+int64_t ne_oracle_extract3(const int64_t *delta, int64_t *dhat, uint8_t *flag,
+                           int64_t N, int w, int l)
+{
+    int64_t bad = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        i128 d0 = (i128)delta[n], d1 = (i128)delta[N + n], d2 = (i128)delta[2 * N + n];
+        i128 dtemp = word2((u128)d2 - (u128)shift_2w(d1, l, w), w);
+        i128 h2 = shift_2w(shift_2w(dtemp, 2 * (w - l), w), -2 * (w - l), w);
+        i128 h0 = shift_2w(word2((u128)0 - (u128)word2((u128)dtemp - (u128)h2, w), w), -2 * l, w);
+        i128 h1 = word2((u128)d1 - (u128)shift_2w(h0, l, w), w);
+        dhat[n] = word((uint64_t)(u128)h0, w);
+        dhat[N + n] = word((uint64_t)(u128)h1, w);
+        dhat[2 * N + n] = word((uint64_t)(u128)h2, w);
+        i128 res = word2((u128)d0 - (u128)word2((u128)shift_2w(h2, l, w) + (u128)h0, w), w);
+        int f = res != 0;
+        if (flag)
+            flag[n] = (uint8_t)f;
+        bad += f;
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------- ABFT */
+
+/*
+ * Checksum stream of section II-A: r_n = sum_m c_{m,n} (one extra stream that
+ * then goes through the same operation).
+ */
+void ne_oracle_abft_checksum(const int64_t *c, int64_t *rsum, int M, int64_t N, int w)
+{
+    for (int64_t n = 0; n < N; ++n) {
+        int64_t s = 0;
+        for (int m = 0; m < M; ++m)
+            s = add_w(s, c[(int64_t)m * N + n], w);
+        rsum[n] = s;
+    }
+}
+
+/*
+ * ABFT check of section II-A: position n is flagged when sum_m d_{m,n} != e_n.
+ * If lost >= 0, the lost output stream is rebuilt as e - sum of the others
+ * (written to d[lost]) instead of checking.  Returns the flag count.
+ */
+int64_t ne_oracle_abft_check(int64_t *d, const int64_t *e, uint8_t *flag, int M,
+                             int64_t N, int w, int lost)
+{
+    int64_t bad = 0;
+    for (int64_t n = 0; n < N; ++n) {
+        if (lost >= 0) {
+            int64_t s = e[n];
+            for (int m = 0; m < M; ++m)
+                if (m != lost)
+                    s = sub_w(s, d[(int64_t)m * N + n], w);
+            d[(int64_t)lost * N + n] = s;
+            continue;
+        }
+        int64_t s = 0;
+        for (int m = 0; m < M; ++m)
+            s = add_w(s, d[(int64_t)m * N + n], w);
+        int f = s != e[n];
+        if (flag)
+            flag[n] = (uint8_t)f;
+        bad += f;
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------- accounting */
+
+/*
+ * Operation counts of section IV (additions plus multiplications), used only
+ * for reporting:  C_GEMM = M N^3, C_conv,time = 4 M N^2,
+ * C_conv,freq = M[(45N+15) log2(3N+1) + 3N + 1], C_ne,conv = 2 M N,
+ * C_ne,GEMM = 2 M N^2, and the checksum-ABFT counts 2MN^2 + C_GEMM/M and
+ * 2MN + C_conv/M.
+ */
+double ne_oracle_opcount(int which, double M, double N)
+{
+    switch (which) {
+    case 0: return M * N * N * N;                         /* C_GEMM */
+    case 1: return 4.0 * M * N * N;                       /* C_conv,time */
+    case 2: {                                             /* C_conv,freq */
+        double lg = log2(3.0 * N + 1.0);
+        return M * ((45.0 * N + 15.0) * lg + 3.0 * N + 1.0);
+    }
+    case 3: return 2.0 * M * N;                           /* C_ne,conv */
+    case 4: return 2.0 * M * N * N;                       /* C_ne,GEMM */
+    case 5: return 2.0 * M * N * N + (M * N * N * N) / M; /* C_ABFT,GEMM */
+    case 6: return 2.0 * M * N + (4.0 * M * N * N) / M;   /* C_ABFT,conv,time */
+    default: return -1.0;
+    }
+}
