@@ -1,0 +1,246 @@
+/*
+ * ne.h -- numerical entanglement on MI355X (gfx950): the C ABI.
+ *
+ * Implements the method of M. A. Anam and Y. Andreopoulos, "Reliable Linear,
+ * Sesquilinear and Bijective Operations on Integer Data Streams via
+ * Numerical Entanglement" (IEEE Trans. Signal Processing; arXiv 1604.04740):
+ * M >= 3 integer streams are entangled in place, an LSB operation runs on the
+ * entangled streams unchanged, and the results are disentangled with
+ * additions and shifts, checked for any single-stream fault, or recovered
+ * from M-1 streams after a fail-stop loss.
+ *
+ * General conventions (every entry point):
+ *   - Pointers named as device pointers must point to device memory of the
+ *     current HIP device (any allocator; 16-byte aligned where stated).
+ *     The caller owns every buffer; the library allocates nothing and keeps
+ *     no global state.
+ *   - Streams are stored stream-major: element n of stream m is at
+ *     [m * N + n] (N = elements per stream); matrices are row-major.
+ *   - Words are w = 64-bit two's complement (int64).  Every word operation
+ *     wraps modulo 2^64; the paper's 2w-bit interim of the disentanglement
+ *     is evaluated exactly.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call is
+ *     asynchronous on that stream.  Argument errors are returned before any
+ *     launch; a failed launch returns NE_ELAUNCH.  Nothing throws.
+ *   - Fault flags are bitmasks: bit (n % 32) of word (n / 32) is set when
+ *     position n fails the reliability check.  Every word of the mask is
+ *     written (no pre-clearing needed).  `n_bad` (a device
+ *     unsigned long long) is INCREMENTED by the number of flagged positions:
+ *     clear it before the first call whose count you want.
+ *   - GPU limits: 3 <= M <= 16 for element-wise entry points, 3 <= M <= 8
+ *     for the fused GEMM; w must be 64; k >= 1.
+ */
+#ifndef NE_H
+#define NE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ return codes */
+#define NE_OK 0
+#define NE_EINVAL (-1)  /* bad M/w/l/k/r, negative size, NULL pointer, bad dtype  */
+#define NE_ERANGE (-2)  /* a-priori output bound exceeds the entangled range D     */
+#define NE_EALIAS (-3)  /* two buffers overlap where they must not                */
+#define NE_EALIGN (-4)  /* a pointer or row pitch is not aligned as required      */
+#define NE_EUNSUP (-5)  /* valid for the method but not built for the GPU         */
+#define NE_ELAUNCH (-6) /* the HIP launch failed                                  */
+
+/* ------------------------------------------------------------- element types */
+#define NE_I8 1
+#define NE_I32 4
+#define NE_I64 8
+
+typedef void *ne_stream_t; /* hipStream_t */
+
+/*
+ * Entanglement parameters (section III-C): M streams, word width w, shift l
+ * and overlap k with (M-1) l + k <= w and k <= l.  r_check selects the
+ * stream that the reliability check rebuilds (any 0 <= r_check < M works;
+ * the detection proofs in the appendix use stream 0).
+ */
+typedef struct ne_params {
+    int32_t M, w, l, k, r_check;
+} ne_params_t;
+
+/* Human-readable message for a return code (static storage). */
+const char *ne_strerror(int code);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int ne_version(void);
+
+/*
+ * (l, k) by the rule of section III-C: maximise the supported output width
+ * (M-2) l + k subject to (M-1) l + k <= w and k <= l.  The paper leaves ties
+ * open (at w = 64 they occur for M = 3 and M = 7); this picks the pair with
+ * (M-1) l + k == w, which guarantees M l >= w (then every single-stream
+ * corruption is detectable, not only bit flips), then the larger l.
+ * Fills *out with r_check = 0.  NE_EINVAL if M < 3, w not in [4, 64], or no
+ * admissible pair exists.
+ */
+int ne_params_default(int32_t M, int32_t w, ne_params_t *out);
+
+/*
+ * The output dynamic range of section III-C: every output d of the LSB
+ * operation must satisfy |d| <= D = 2^((M-3) l + k) (2^(l-1) - 1) for
+ * extraction to be exact.  NE_EINVAL on invalid parameters.
+ */
+int ne_range_bound(const ne_params_t *p, int64_t *D);
+
+/*
+ * Entanglement, section III-C (the circulant operator E; section III-A for
+ * M = 3): for every position n and stream m,
+ *     eps[m][n] = c[m][n] + 2^l * c[(m - 1) mod M][n]    (mod 2^64).
+ *   c       device, [M][N] elements of type c_dtype (NE_I8, NE_I32, NE_I64).
+ *   eps     device, [M][N] int64.  May equal c when c_dtype == NE_I64 (in
+ *           place, as the paper stores entangled streams in place of the
+ *           inputs); must not otherwise overlap c.
+ *   N       elements per stream, >= 0.
+ */
+int ne_entangle(const void *c, int32_t c_dtype, int64_t *eps, int64_t N,
+                const ne_params_t *p, ne_stream_t stream);
+
+/*
+ * The GEMM of section III-A applied, unchanged, to the entangled streams:
+ *     delta[m] = eps[m] * G     (int64 words, mod 2^64),
+ * for every stream m, with G the shared operand.  The routine is unaware of
+ * entanglement: it treats eps as generic 64-bit words, split into signed
+ * int8 digits on int8 matrix cores with exact int32 accumulation.
+ *   eps       device, [M][n][K] int64.
+ *   eps_bits  bound on the words: every eps value lies in
+ *             [-2^(eps_bits-1), 2^(eps_bits-1)); 1..64.  Sets the digit count
+ *             min(8, eps_bits/8 + 1); 64 is always safe.
+ *   Gt        device, the shared operand TRANSPOSED: Gt[j][k] = G[k][j],
+ *             [N][K] int8 (K contiguous, the layout int8 matrix cores read).
+ *   delta     device, [M][n][N] int64; must not overlap eps or Gt.
+ *   K         <= 131071 (keeps every int32 digit accumulator exact).
+ */
+int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t *delta,
+                int64_t n, int64_t K, int64_t N, const ne_params_t *p, ne_stream_t stream);
+
+/*
+ * Circular convolution of each entangled stream with the shared kernel g
+ * (section II, the star operator):
+ *     delta[m][t] = sum_{j=0}^{N-1} eps[m][(t - j) mod N] * g[j]   (mod 2^64).
+ *   eps       device, [M][N] int64;  eps_bits as for ne_lsb_gemm.
+ *   g         device, [N] int8.
+ *   delta     device, [M][N] int64; must not overlap eps.
+ *   N         1 .. 131071 (exact int32 digit accumulation).
+ */
+int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
+                    int64_t N, const ne_params_t *p, ne_stream_t stream);
+
+/*
+ * Fixed permutation, scaling and addition on the entangled streams (section
+ * II, op in {permutation, x, +}; the constant is self-entangled as the
+ * footnote of section III-A requires for + and -):
+ *     delta[m][n] = scale[n] * eps[m][perm[n]] + (2^l + 1) * add[n]  (mod 2^64)
+ *   perm      device, [N] int32, a bijection of 0..N-1 (values out of range
+ *             are clamped, never read out of bounds).
+ *   scale     device, [N] int64, or NULL for 1.
+ *   add       device, [N] int64 un-entangled constant, or NULL for 0.
+ *   delta     device, [M][N] int64; must not overlap eps.
+ */
+int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
+                         const int64_t *add, int64_t *delta, int64_t N,
+                         const ne_params_t *p, ne_stream_t stream);
+
+/*
+ * Disentanglement and the post-computation reliability check (section
+ * III-C; the check of the generalised detection proof in the appendix),
+ * with r = p->r_check:
+ *     d_temp = (-1)^M sum_{m=0}^{M-2} (-1)^m 2^((M-2-m) l) delta[(r+1+m) mod M]
+ *     d_hat[(r+M-1) mod M] = sign-extended low (M-1) l bits of d_temp
+ *     d_hat[r] = (-1)^M (d_temp - d_hat[(r+M-1) mod M]) >> (M-1) l
+ *     d_hat[(r+m) mod M] = delta[(r+m) mod M] - 2^l d_hat[(r+m-1) mod M], 1 <= m <= M-2
+ *     flag[n] = delta[r][n] != d_hat[r][n] + 2^l d_hat[(r+M-1) mod M][n]  (exact)
+ * (the leading (-1)^M and the chain bound m <= M-2 are the readings of the
+ * printed formulas that make them exact for every M; for M = 3 they reduce
+ * to the special form of section III-A).  d_hat keeps the low 64 bits.
+ *   delta     device, [M][N] int64.
+ *   d_hat     device, [M][N] int64; may equal delta (in place).
+ *   flags     device, [ceil(N/32)] uint32 bitmask, or NULL.
+ *   n_bad     device counter (incremented), or NULL.
+ */
+int ne_disentangle_check(const int64_t *delta, int64_t *d_hat, uint32_t *flags,
+                         unsigned long long *n_bad, int64_t N, const ne_params_t *p,
+                         ne_stream_t stream);
+
+/*
+ * Fail-stop recovery (Propositions 1 and 3): every output from the M-1
+ * surviving entangled streams, i.e. the disentanglement above with r = lost.
+ *   delta          HOST array of M device pointers to the [N] int64 output
+ *                  of each stream; delta[lost] is never read (may be NULL).
+ *   lost           0 <= lost < M.
+ *   d_hat          device, [M][N] int64; must not overlap any delta[m].
+ *   delta_rebuilt  device, [N] int64 or NULL: the lost stream re-created as
+ *                  d_hat[lost] + 2^l d_hat[(lost+M-1) mod M] (mod 2^64).
+ */
+int ne_recover(const int64_t *const *delta, int32_t lost, int64_t *d_hat,
+               int64_t *delta_rebuilt, int64_t N, const ne_params_t *p, ne_stream_t stream);
+
+/*
+ * Optional fault injection into the fused GEMM (for measuring detection):
+ * before extraction, entangled output word delta[stream[i]] at flat position
+ * position[i] (= row * N + col) is XOR-ed with xor_mask[i].  Positions must
+ * be sorted ascending.  All arrays are device arrays of length count.
+ */
+typedef struct ne_inject {
+    int64_t count;
+    const int64_t *position;
+    const int32_t *stream;
+    const uint64_t *xor_mask;
+} ne_inject_t;
+
+/*
+ * The fused hot path for the GEMM of section III-A on int8 inputs, one
+ * launch: entangle in the prologue, int8-matrix-core GEMM on the entangled
+ * words, then disentangle and check in the epilogue; delta never reaches
+ * memory.  For stream m the entangled word is c[m] + 2^l c[m-1 mod M], whose
+ * signed int8 digits at bit offsets 0 and l are c[m] and c[m-1]; each is
+ * multiplied by G on its own (so a fault in one stream's product stays in
+ * that stream), and delta[m] = P_lo + 2^l P_hi is formed in int64.
+ *   c         device, [M][n][K] int8 (16-byte aligned; K % 16 == 0 is the
+ *             fast path, any K works).
+ *   Gt        device, [N][K] int8, the shared operand transposed.
+ *   d_hat     device, [M][n][N] of out_dtype (NE_I32 or NE_I64; I32 keeps
+ *             the low 32 bits, exact whenever |d| < 2^31, which holds for
+ *             K <= 131071 on int8 inputs).
+ *   flags     device bitmask, ROW-PADDED: [n][ceil(N/32)] uint32 (bit
+ *             (col % 32) of word [row][col / 32]), or NULL.
+ *   n_bad     device counter (incremented), or NULL.
+ *   inject    HOST pointer to an injection table (device arrays), or NULL.
+ * NE_ERANGE if K * 128 * 128 > D (the a-priori bound for int8 data).
+ */
+int ne_gemm_fused(const int8_t *c, const int8_t *Gt, void *d_hat, int32_t out_dtype,
+                  uint32_t *flags, unsigned long long *n_bad, int64_t n, int64_t K, int64_t N,
+                  const ne_params_t *p, const ne_inject_t *inject, ne_stream_t stream);
+
+/*
+ * Baseline: the plain (fault-intolerant) int8 GEMM of the stacked streams,
+ * C[R][N] = A[R][K] * B (int32), with B given transposed as Bt[N][K].
+ * Same matrix-core pipeline as the fused path.  K <= 131071.
+ */
+int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,
+                     int64_t N, ne_stream_t stream);
+
+/*
+ * Baseline: checksum-stream ABFT of section II-A for the same GEMM, one
+ * launch.  The checksum stream r = sum_m c[m] is built in the prologue
+ * (two signed int8 digits, since |r| <= 128 M), multiplied by G alongside
+ * the M streams, and the epilogue flags positions where
+ * sum_m d[m] != e (section II-A).
+ *   c  device [M][n][K] int8;  Gt device [N][K] int8;
+ *   d  device [M][n][N] int32;  flags row-padded as for ne_gemm_fused.
+ */
+int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *flags,
+                    unsigned long long *n_bad, int32_t M, int64_t n, int64_t K, int64_t N,
+                    ne_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NE_H */

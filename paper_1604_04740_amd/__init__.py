@@ -1,0 +1,324 @@
+"""Numerical entanglement on MI355X: Python binding of the C ABI (libne.so).
+
+Argument marshalling only: every function here checks tensor placement,
+dtype and shape, passes raw device pointers and the current HIP stream to
+the function of the same name in include/ne.h, and raises NEError on a
+non-zero return code.  All computation happens in the library's HIP
+kernels; there is no other code path.  Importing works without a GPU (the
+library's argument checks and parameter rules run on the host), but any call
+that launches work needs a ROCm device.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+__all__ = [
+    "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
+    "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
+    "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
+    "Inject",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libne.so")
+
+NE_I8, NE_I32, NE_I64 = 1, 4, 8
+_DT = {torch.int8: NE_I8, torch.int32: NE_I32, torch.int64: NE_I64}
+
+
+class NEError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {ne_strerror(code)} (code {code})")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("w", ctypes.c_int32), ("l", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("r_check", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"Params(M={self.M}, w={self.w}, l={self.l}, k={self.k}, r_check={self.r_check})"
+
+
+class _Inject(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("position", ctypes.c_void_p),
+                ("stream", ctypes.c_void_p), ("xor_mask", ctypes.c_void_p)]
+
+
+_lib = None
+_vp, _i32, _i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+
+
+def lib():
+    """The loaded libne.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(Params)
+        sig = {
+            "ne_strerror": ([ctypes.c_int], ctypes.c_char_p),
+            "ne_version": ([], ctypes.c_int),
+            "ne_params_default": ([_i32, _i32, P], ctypes.c_int),
+            "ne_range_bound": ([P, ctypes.POINTER(_i64)], ctypes.c_int),
+            "ne_entangle": ([_vp, _i32, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_lsb_gemm": ([_vp, _i32, _vp, _vp, _i64, _i64, _i64, P, _vp], ctypes.c_int),
+            "ne_lsb_circconv": ([_vp, _i32, _vp, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_lsb_permute_scale": ([_vp, _vp, _vp, _vp, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_disentangle_check": ([_vp, _vp, _vp, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_recover": ([ctypes.POINTER(_vp), _i32, _vp, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_gemm_fused": ([_vp, _vp, _vp, _i32, _vp, _vp, _i64, _i64, _i64, P,
+                               ctypes.POINTER(_Inject), _vp], ctypes.c_int),
+            "ne_plain_gemm_i8": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp], ctypes.c_int),
+            "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp],
+                                ctypes.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def ne_strerror(code: int) -> str:
+    return lib().ne_strerror(code).decode()
+
+
+def ne_version() -> int:
+    return lib().ne_version()
+
+
+def _ok(code: int, where: str):
+    if code != 0:
+        raise NEError(code, where)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a ROCm device")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, name, dtype):
+    return _dev(t, name, dtype) if t is not None else None
+
+
+# --------------------------------------------------------------- parameters
+
+def ne_params_default(M: int, w: int = 64) -> Params:
+    p = Params()
+    _ok(lib().ne_params_default(M, w, ctypes.byref(p)), "ne_params_default")
+    return p
+
+
+def ne_range_bound(p: Params) -> int:
+    D = _i64()
+    _ok(lib().ne_range_bound(ctypes.byref(p), ctypes.byref(D)), "ne_range_bound")
+    return D.value
+
+
+# --------------------------------------------------------------- staged path
+
+def ne_entangle(c: torch.Tensor, p: Params, out: torch.Tensor | None = None) -> torch.Tensor:
+    """c: [M, ...] int8/int32/int64 -> eps [M, ...] int64 (out may be c if int64)."""
+    if c.dtype not in _DT:
+        raise TypeError("c must be int8, int32 or int64")
+    M = c.shape[0]
+    if M != p.M:
+        raise ValueError("leading dimension must be M")
+    if out is None:
+        out = torch.empty(c.shape, dtype=torch.int64, device=c.device)
+    if out.shape != c.shape:
+        raise ValueError("out must have the shape of c")
+    N = c.numel() // M if M else 0
+    _ok(lib().ne_entangle(_dev(c, "c"), _DT[c.dtype], _dev(out, "out", torch.int64), N,
+                          ctypes.byref(p), _stream()), "ne_entangle")
+    return out
+
+
+def ne_lsb_gemm(eps: torch.Tensor, eps_bits: int, Gt: torch.Tensor, p: Params,
+                out: torch.Tensor | None = None) -> torch.Tensor:
+    """eps: [M, n, K] int64, Gt: [N, K] int8 -> delta [M, n, N] int64."""
+    M, n, K = eps.shape
+    N, K2 = Gt.shape
+    if K2 != K or M != p.M:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((M, n, N), dtype=torch.int64, device=eps.device)
+    _ok(lib().ne_lsb_gemm(_dev(eps, "eps", torch.int64), eps_bits, _dev(Gt, "Gt", torch.int8),
+                          _dev(out, "out", torch.int64), n, K, N, ctypes.byref(p), _stream()),
+        "ne_lsb_gemm")
+    return out
+
+
+def ne_lsb_circconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,
+                    out: torch.Tensor | None = None) -> torch.Tensor:
+    """eps: [M, N] int64, g: [N] int8 -> delta [M, N] int64."""
+    M, N = eps.shape
+    if g.shape != (N,) or M != p.M:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty_like(eps)
+    _ok(lib().ne_lsb_circconv(_dev(eps, "eps", torch.int64), eps_bits, _dev(g, "g", torch.int8),
+                              _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
+        "ne_lsb_circconv")
+    return out
+
+
+def ne_lsb_permute_scale(eps: torch.Tensor, perm: torch.Tensor, scale: torch.Tensor | None,
+                         add: torch.Tensor | None, p: Params,
+                         out: torch.Tensor | None = None) -> torch.Tensor:
+    """eps: [M, N] int64; perm [N] int32; scale/add [N] int64 or None."""
+    M, N = eps.shape
+    if M != p.M or perm.shape != (N,):
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty_like(eps)
+    _ok(lib().ne_lsb_permute_scale(_dev(eps, "eps", torch.int64), _dev(perm, "perm", torch.int32),
+                                   _opt(scale, "scale", torch.int64), _opt(add, "add", torch.int64),
+                                   _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
+        "ne_lsb_permute_scale")
+    return out
+
+
+def ne_disentangle_check(delta: torch.Tensor, p: Params, out: torch.Tensor | None = None,
+                         flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+    """delta: [M, ...] int64 -> (d_hat [M, ...] int64, flags uint32 words or None, n_bad)."""
+    M = delta.shape[0]
+    if M != p.M:
+        raise ValueError("leading dimension must be M")
+    N = delta.numel() // M
+    if out is None:
+        out = torch.empty_like(delta)
+    if flags is True:
+        flags = torch.empty(((N + 31) // 32,), dtype=torch.int32, device=delta.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=delta.device)
+    _ok(lib().ne_disentangle_check(_dev(delta, "delta", torch.int64), _dev(out, "out", torch.int64),
+                                   _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
+                                   N, ctypes.byref(p), _stream()), "ne_disentangle_check")
+    return out, flags, n_bad
+
+
+def ne_recover(deltas, lost: int, p: Params, rebuild: bool = False, out: torch.Tensor | None = None):
+    """deltas: list of M tensors [N] int64 (deltas[lost] may be None).
+    Returns (d_hat [M, N] int64, rebuilt [N] int64 or None)."""
+    M = p.M
+    if len(deltas) != M:
+        raise ValueError("need M stream pointers")
+    ref = next(d for i, d in enumerate(deltas) if i != lost)
+    N = ref.numel()
+    ptrs = (_vp * M)()
+    for i, d in enumerate(deltas):
+        if i == lost:
+            ptrs[i] = None
+            continue
+        if d.numel() != N:
+            raise ValueError("every stream must have N words")
+        ptrs[i] = _dev(d, f"deltas[{i}]", torch.int64).value
+    if out is None:
+        out = torch.empty((M,) + tuple(ref.shape), dtype=torch.int64, device=ref.device)
+    rb = torch.empty_like(ref) if rebuild else None
+    _ok(lib().ne_recover(ptrs, lost, _dev(out, "out", torch.int64), _opt(rb, "rebuilt", torch.int64),
+                         N, ctypes.byref(p), _stream()), "ne_recover")
+    return out, rb
+
+
+# --------------------------------------------------------------- fused path
+
+class Inject:
+    """Device-side fault list for ne_gemm_fused: XOR xor_mask into the entangled
+    output word of `stream` at flat position `position` (row * N + col)."""
+
+    def __init__(self, position: torch.Tensor, stream: torch.Tensor, xor_mask: torch.Tensor):
+        order = torch.argsort(position)
+        self.position = position[order].to(torch.int64).contiguous()
+        self.stream = stream[order].to(torch.int32).contiguous()
+        self.xor_mask = xor_mask[order].to(torch.int64).contiguous()
+
+    def struct(self):
+        s = _Inject()
+        s.count = self.position.numel()
+        s.position = _dev(self.position, "position", torch.int64)
+        s.stream = _dev(self.stream, "stream", torch.int32)
+        s.xor_mask = _dev(self.xor_mask, "xor_mask", torch.int64)
+        return s
+
+
+def ne_gemm_fused(c: torch.Tensor, Gt: torch.Tensor, p: Params, out_dtype=torch.int32,
+                  out: torch.Tensor | None = None, flags: bool | torch.Tensor = True,
+                  n_bad: torch.Tensor | None = None, inject: Inject | None = None):
+    """c: [M, n, K] int8, Gt: [N, K] int8 -> (d_hat [M, n, N], flags [n, ceil(N/32)], n_bad)."""
+    M, n, K = c.shape
+    N, K2 = Gt.shape
+    if K2 != K or M != p.M:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((M, n, N), dtype=out_dtype, device=c.device)
+    if flags is True:
+        flags = torch.empty((n, (N + 31) // 32), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    inj = ctypes.byref(inject.struct()) if inject is not None else None
+    _ok(lib().ne_gemm_fused(_dev(c, "c", torch.int8), _dev(Gt, "Gt", torch.int8),
+                            _dev(out, "out", out_dtype), _DT[out_dtype],
+                            _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
+                            n, K, N, ctypes.byref(p), inj, _stream()), "ne_gemm_fused")
+    return out, flags, n_bad
+
+
+def ne_plain_gemm_i8(A: torch.Tensor, Bt: torch.Tensor, out: torch.Tensor | None = None):
+    """A: [R, K] int8 (or [M, n, K]), Bt: [N, K] int8 -> C int32 [R, N] (or [M, n, N])."""
+    K = A.shape[-1]
+    R = math.prod(A.shape[:-1])
+    N, K2 = Bt.shape
+    if K2 != K:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty(tuple(A.shape[:-1]) + (N,), dtype=torch.int32, device=A.device)
+    _ok(lib().ne_plain_gemm_i8(_dev(A, "A", torch.int8), _dev(Bt, "Bt", torch.int8),
+                               _dev(out, "out", torch.int32), R, K, N, _stream()), "ne_plain_gemm_i8")
+    return out
+
+
+def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None = None,
+                    flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+    """c: [M, n, K] int8, Gt: [N, K] int8 -> (d [M, n, N] int32, flags, n_bad)."""
+    M, n, K = c.shape
+    N, K2 = Gt.shape
+    if K2 != K:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((M, n, N), dtype=torch.int32, device=c.device)
+    if flags is True:
+        flags = torch.empty((n, (N + 31) // 32), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    _ok(lib().ne_abft_gemm_i8(_dev(c, "c", torch.int8), _dev(Gt, "Gt", torch.int8),
+                              _dev(out, "out", torch.int32), _opt(flags, "flags", torch.int32),
+                              _dev(n_bad, "n_bad", torch.int64), M, n, K, N, _stream()),
+        "ne_abft_gemm_i8")
+    return out, flags, n_bad
+

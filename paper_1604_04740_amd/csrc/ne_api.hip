@@ -1,0 +1,311 @@
+// ne_api.hip -- the C ABI declared in include/ne.h: argument validation,
+// parameter rules, and dispatch to the kernels.  No allocation, no global
+// state; every launch goes to the caller's stream.
+#include <stdint.h>
+
+#include "ne_arith.h"
+#include "ne_internal.h"
+
+using namespace ne;
+
+namespace {
+
+constexpr int kVersion = 100; // 0.1.0
+
+bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes)
+{
+    if (!a || !b || abytes <= 0 || bbytes <= 0)
+        return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + (uintptr_t)bbytes && b0 < a0 + (uintptr_t)abytes;
+}
+
+// Parameters admissible for the method (section III-C) and built for the GPU.
+int check_params(const ne_params_t *p, int max_m)
+{
+    if (!p)
+        return NE_EINVAL;
+    if (p->M < 3 || p->w < 4 || p->w > 64 || p->l < 2 || p->k < 0 || p->k > p->l ||
+        (int64_t)(p->M - 1) * p->l + p->k > p->w || p->r_check < 0 || p->r_check >= p->M)
+        return NE_EINVAL;
+    if (p->w != 64 || p->M > max_m)
+        return NE_EUNSUP;
+    return NE_OK;
+}
+
+hipStream_t hs(ne_stream_t s) { return (hipStream_t)s; }
+
+} // namespace
+
+extern "C" {
+
+const char *ne_strerror(int code)
+{
+    switch (code) {
+    case NE_OK: return "success";
+    case NE_EINVAL: return "invalid argument";
+    case NE_ERANGE: return "output range exceeds the entangled dynamic range";
+    case NE_EALIAS: return "buffers overlap";
+    case NE_EALIGN: return "misaligned pointer or pitch";
+    case NE_EUNSUP: return "not supported on this GPU build";
+    case NE_ELAUNCH: return "kernel launch failed";
+    default: return "unknown error";
+    }
+}
+
+int ne_version(void) { return kVersion; }
+
+int ne_params_default(int32_t M, int32_t w, ne_params_t *out)
+{
+    if (!out || M < 3 || w < 4 || w > 64)
+        return NE_EINVAL;
+    // Scan l; for each l the best overlap is k = min(l, w - (M-1) l).
+    int best_l = -1, best_k = -1, best_width = -1;
+    bool best_fills = false;
+    for (int l = 1; (M - 1) * l <= w; ++l) {
+        const int room = w - (M - 1) * l;
+        const int k = room < l ? room : l;
+        const int width = (M - 2) * l + k;
+        const bool fills = (k == room);
+        if (width > best_width || (width == best_width && fills && !best_fills) ||
+            (width == best_width && fills == best_fills && l > best_l)) {
+            best_width = width;
+            best_l = l;
+            best_k = k;
+            best_fills = fills;
+        }
+    }
+    if (best_l < 0)
+        return NE_EINVAL;
+    out->M = M;
+    out->w = w;
+    out->l = best_l;
+    out->k = best_k;
+    out->r_check = 0;
+    return NE_OK;
+}
+
+int ne_range_bound(const ne_params_t *p, int64_t *D)
+{
+    if (!p || !D || p->M < 3 || p->l < 2 || p->k < 0 || p->k > p->l ||
+        (int64_t)(p->M - 1) * p->l + p->k > p->w || p->w > 64)
+        return NE_EINVAL;
+    const int e = (p->M - 3) * p->l + p->k; // <= w - 2l <= 60
+    *D = ((int64_t)1 << e) * (((int64_t)1 << (p->l - 1)) - 1);
+    return NE_OK;
+}
+
+int ne_entangle(const void *c, int32_t c_dtype, int64_t *eps, int64_t N, const ne_params_t *p,
+                ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (N < 0 || (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64))
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!c || !eps)
+        return NE_EINVAL;
+    const int64_t cb = N * p->M * c_dtype, eb = N * p->M * 8;
+    const bool same = (const void *)eps == c;
+    if (same && c_dtype != NE_I64)
+        return NE_EALIAS;
+    if (!same && overlap(c, cb, eps, eb))
+        return NE_EALIAS;
+    if (((uintptr_t)c % c_dtype) || ((uintptr_t)eps % 8))
+        return NE_EALIGN;
+    return launch_entangle(c, c_dtype, eps, N, p->M, p->l, hs(stream));
+}
+
+int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t *delta,
+                int64_t n, int64_t K, int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (n < 0 || K < 0 || N < 0 || K > kMaxK || eps_bits < 1 || eps_bits > 64)
+        return NE_EINVAL;
+    if (n == 0 || N == 0)
+        return NE_OK;
+    if (!eps || !Gt || !delta)
+        return NE_EINVAL;
+    const int64_t R = n * p->M;
+    if (overlap(eps, R * K * 8, delta, R * N * 8) || overlap(Gt, N * K, delta, R * N * 8))
+        return NE_EALIAS;
+    if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8)
+        return NE_EALIGN;
+    return launch_gemm_eps(eps, ne::digits_for_bits(eps_bits), Gt, delta, R, K, N,
+                           hs(stream));
+}
+
+int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
+                    int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (N < 0 || N > kMaxK || eps_bits < 1 || eps_bits > 64)
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!eps || !g || !delta)
+        return NE_EINVAL;
+    const int64_t bytes = N * p->M * 8;
+    if (overlap(eps, bytes, delta, bytes) || overlap(g, N, delta, bytes))
+        return NE_EALIAS;
+    if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8)
+        return NE_EALIGN;
+    return launch_circconv_eps(eps, ne::digits_for_bits(eps_bits), g, delta, N, p->M,
+                               hs(stream));
+}
+
+int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
+                         const int64_t *add, int64_t *delta, int64_t N, const ne_params_t *p,
+                         ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (N < 0 || N > 0x7fffffff)
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!eps || !perm || !delta)
+        return NE_EINVAL;
+    const int64_t bytes = N * p->M * 8;
+    if (overlap(eps, bytes, delta, bytes) || overlap(perm, N * 4, delta, bytes) ||
+        overlap(scale, N * 8, delta, bytes) || overlap(add, N * 8, delta, bytes))
+        return NE_EALIAS;
+    if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8 || (uintptr_t)perm % 4 ||
+        (uintptr_t)scale % 8 || (uintptr_t)add % 8)
+        return NE_EALIGN;
+    return launch_permute_scale(eps, perm, scale, add, delta, N, p->M, p->l, hs(stream));
+}
+
+int ne_disentangle_check(const int64_t *delta, int64_t *d_hat, uint32_t *flags,
+                         unsigned long long *n_bad, int64_t N, const ne_params_t *p,
+                         ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (N < 0)
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!delta || !d_hat)
+        return NE_EINVAL;
+    const int64_t bytes = N * p->M * 8;
+    if (d_hat != delta && overlap(delta, bytes, d_hat, bytes))
+        return NE_EALIAS;
+    if (overlap(flags, ((N + 31) / 32) * 4, d_hat, bytes) ||
+        overlap(flags, ((N + 31) / 32) * 4, delta, bytes))
+        return NE_EALIAS;
+    if ((uintptr_t)delta % 8 || (uintptr_t)d_hat % 8 || (uintptr_t)flags % 4 ||
+        (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_disentangle_check(delta, d_hat, flags, n_bad, N, p->M, p->l, p->r_check,
+                                    hs(stream));
+}
+
+int ne_recover(const int64_t *const *delta, int32_t lost, int64_t *d_hat, int64_t *delta_rebuilt,
+               int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (!delta || lost < 0 || lost >= p->M || N < 0)
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!d_hat)
+        return NE_EINVAL;
+    StreamPtrs sp{};
+    const int64_t out_bytes = N * p->M * 8;
+    for (int m = 0; m < p->M; ++m) {
+        if (m == lost)
+            continue;
+        if (!delta[m])
+            return NE_EINVAL;
+        if (overlap(delta[m], N * 8, d_hat, out_bytes) ||
+            overlap(delta[m], N * 8, delta_rebuilt, N * 8))
+            return NE_EALIAS;
+        if ((uintptr_t)delta[m] % 8)
+            return NE_EALIGN;
+        sp.p[m] = delta[m];
+    }
+    if (overlap(delta_rebuilt, N * 8, d_hat, out_bytes))
+        return NE_EALIAS;
+    if ((uintptr_t)d_hat % 8 || (uintptr_t)delta_rebuilt % 8)
+        return NE_EALIGN;
+    return launch_recover(sp, lost, d_hat, delta_rebuilt, N, p->M, p->l, hs(stream));
+}
+
+int ne_gemm_fused(const int8_t *c, const int8_t *Gt, void *d_hat, int32_t out_dtype,
+                  uint32_t *flags, unsigned long long *n_bad, int64_t n, int64_t K, int64_t N,
+                  const ne_params_t *p, const ne_inject_t *inject, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsFused);
+    if (rc)
+        return rc;
+    if (n < 0 || K < 0 || N < 0 || K > kMaxK || (out_dtype != NE_I32 && out_dtype != NE_I64))
+        return NE_EINVAL;
+    int64_t D = 0;
+    ne_range_bound(p, &D);
+    if (K * 128 * 128 > D)
+        return NE_ERANGE;
+    if (inject && inject->count > 0 &&
+        (!inject->position || !inject->stream || !inject->xor_mask))
+        return NE_EINVAL;
+    if (n == 0 || N == 0)
+        return NE_OK;
+    if (!c || !Gt || !d_hat)
+        return NE_EINVAL;
+    const int64_t ob = p->M * n * N * out_dtype;
+    const int64_t fb = n * ((N + 31) / 32) * 4;
+    if (overlap(c, p->M * n * K, d_hat, ob) || overlap(Gt, N * K, d_hat, ob) ||
+        overlap(flags, fb, d_hat, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_gemm_fused(c, Gt, d_hat, out_dtype == NE_I64, flags, n_bad, n, K, N, p->M, p->l,
+                             p->r_check, inject, hs(stream));
+}
+
+int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,
+                     int64_t N, ne_stream_t stream)
+{
+    if (R < 0 || K < 0 || N < 0 || K > kMaxK)
+        return NE_EINVAL;
+    if (R == 0 || N == 0)
+        return NE_OK;
+    if (!A || !Bt || !C)
+        return NE_EINVAL;
+    if (overlap(A, R * K, C, R * N * 4) || overlap(Bt, N * K, C, R * N * 4))
+        return NE_EALIAS;
+    if ((uintptr_t)C % 4)
+        return NE_EALIGN;
+    return launch_gemm_plain(A, Bt, C, R, K, N, hs(stream));
+}
+
+int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *flags,
+                    unsigned long long *n_bad, int32_t M, int64_t n, int64_t K, int64_t N,
+                    ne_stream_t stream)
+{
+    if (M < 1 || M > kMaxStreamsFused || n < 0 || K < 0 || N < 0 || K > kMaxK)
+        return NE_EINVAL;
+    if (n == 0 || N == 0)
+        return NE_OK;
+    if (!c || !Gt || !d)
+        return NE_EINVAL;
+    const int64_t ob = (int64_t)M * n * N * 4;
+    if (overlap(c, (int64_t)M * n * K, d, ob) || overlap(Gt, N * K, d, ob) ||
+        overlap(flags, n * ((N + 31) / 32) * 4, d, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)d % 4 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_gemm_abft(c, Gt, d, flags, n_bad, n, K, N, M, hs(stream));
+}
+
+} // extern "C"

@@ -1,0 +1,68 @@
+// ne_internal.h -- declarations shared by the library's translation units
+// (launchers called by the C-ABI layer in ne_api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ne.h"
+
+namespace ne {
+
+// Maximum number of streams handled by the element-wise kernels.
+constexpr int kMaxStreamsElementwise = 16;
+// Maximum number of streams handled by the fused GEMM.
+constexpr int kMaxStreamsFused = 8;
+// Largest K (or convolution length) whose int8 x int8 digit products,
+// summed, always fit an int32 accumulator: K * 128 * 128 <= 2^31 - 1.
+constexpr int64_t kMaxK = 131071;
+
+struct StreamPtrs {
+    const int64_t *p[kMaxStreamsElementwise];
+};
+
+// ---- element-wise kernels (ne_elementwise.hip) ----
+int launch_entangle(const void *c, int c_dtype, int64_t *eps, int64_t N, int M, int l,
+                    hipStream_t s);
+int launch_disentangle_check(const int64_t *delta, int64_t *dhat, uint32_t *flags,
+                             unsigned long long *n_bad, int64_t N, int M, int l, int r,
+                             hipStream_t s);
+int launch_recover(const StreamPtrs &delta, int lost, int64_t *dhat, int64_t *rebuilt,
+                   int64_t N, int M, int l, hipStream_t s);
+int launch_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
+                         const int64_t *add, int64_t *delta, int64_t N, int M, int l,
+                         hipStream_t s);
+
+// ---- matrix-core GEMMs (ne_gemm.hip) ----
+int launch_gemm_plain(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,
+                      int64_t N, hipStream_t s);
+int launch_gemm_eps(const int64_t *eps, int digits, const int8_t *Bt, int64_t *delta, int64_t R,
+                    int64_t K, int64_t N, hipStream_t s);
+int launch_gemm_fused(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uint32_t *flags,
+                      unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M, int l,
+                      int r, const ne_inject_t *inj, hipStream_t s);
+int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
+                     unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M,
+                     hipStream_t s);
+
+// ---- circular convolution (ne_conv.hip) ----
+int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
+                        int64_t N, int M, hipStream_t s);
+
+// Grid size for grid-stride element-wise kernels.
+inline unsigned grid_for(int64_t work, int threads)
+{
+    int64_t blocks = (work + threads - 1) / threads;
+    if (blocks > 8192)
+        blocks = 8192;
+    if (blocks < 1)
+        blocks = 1;
+    return (unsigned)blocks;
+}
+
+inline int launch_status()
+{
+    return hipGetLastError() == hipSuccess ? NE_OK : NE_ELAUNCH;
+}
+
+} // namespace ne

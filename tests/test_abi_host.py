@@ -1,0 +1,97 @@
+"""CPU tests of the C ABI's host logic: the library loads, exports every
+symbol include/ne.h declares, applies the paper's parameter rule, and
+rejects bad arguments before any launch (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def ne():
+    import paper_1604_04740_amd as ne
+    ne.lib()
+    return ne
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ne.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ne_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(ne):
+    names = _declared()
+    assert "ne_gemm_fused" in names and "ne_recover" in names
+    for n in names:
+        assert hasattr(ne.lib(), n), n
+
+
+def test_params_rule_matches_oracle(ne, orc):
+    for w in (16, 24, 32, 48, 64):
+        for M in range(3, 33):
+            try:
+                ref = orc.params(M, w)
+            except ValueError:
+                continue
+            p = ne.ne_params_default(M, w)
+            assert (p.l, p.k) == ref, (M, w)
+            if ref[0] >= 2 and w == 64:
+                assert ne.ne_range_bound(p) == orc.range_bound(M, *ref)
+
+
+def test_argument_errors_before_launch(ne):
+    L = ne.lib()
+    P = ne.Params
+    bad = [P(2, 64, 22, 20, 0), P(3, 64, 22, 23, 0), P(3, 64, 30, 20, 0), P(3, 64, 22, 20, 3),
+           P(3, 64, 1, 1, 0)]
+    for p in bad:
+        rc = L.ne_disentangle_check(ctypes.c_void_p(16), ctypes.c_void_p(64), None, None, 10,
+                                    ctypes.byref(p), None)
+        assert rc == -1, p
+    # valid for the method, not built for the GPU: w = 32
+    p = ne.ne_params_default(3, 32)
+    rc = L.ne_disentangle_check(ctypes.c_void_p(16), ctypes.c_void_p(64), None, None, 10,
+                                ctypes.byref(p), None)
+    assert rc == -5
+    p = ne.ne_params_default(3)
+    # overlapping delta / d_hat (not identical)
+    rc = L.ne_disentangle_check(ctypes.c_void_p(4096), ctypes.c_void_p(4096 + 8), None, None, 10,
+                                ctypes.byref(p), None)
+    assert rc == -3
+    # misaligned
+    rc = L.ne_disentangle_check(ctypes.c_void_p(4097), ctypes.c_void_p(1 << 20), None, None, 10,
+                                ctypes.byref(p), None)
+    assert rc == -4
+    # K too large for exact int32 digit accumulation
+    rc = L.ne_lsb_gemm(ctypes.c_void_p(16), 64, ctypes.c_void_p(1 << 30), ctypes.c_void_p(1 << 31),
+                       4, 131072, 4, ctypes.byref(p), None)
+    assert rc == -1
+    # fused: M beyond the fused build
+    p9 = ne.ne_params_default(9)
+    rc = L.ne_gemm_fused(ctypes.c_void_p(16), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30),
+                         4, None, None, 4, 16, 4, ctypes.byref(p9), None, None)
+    assert rc == -5
+    # empty inputs are a no-op success, even with NULL buffers
+    rc = L.ne_entangle(None, 8, None, 0, ctypes.byref(p), None)
+    assert rc == 0
+    assert ne.ne_strerror(-2).startswith("output range")
+
+
+def test_range_rejection_fused(ne):
+    """The a-priori bound K * 128 * 128 must not exceed D (section III-C)."""
+    L = ne.lib()
+    p = ne.Params(3, 64, 22, 20, 0)
+    D = ne.ne_range_bound(p)
+    K_ok = D // (128 * 128)
+    assert K_ok > 131071  # every admissible K fits at w = 64, M = 3
+    # a narrower l makes the bound bite
+    p_small = ne.Params(3, 64, 10, 10, 0)
+    D2 = ne.ne_range_bound(p_small)
+    K_bad = D2 // (128 * 128) + 1
+    rc = L.ne_gemm_fused(ctypes.c_void_p(16), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30),
+                         4, None, None, 4, K_bad, 4, ctypes.byref(p_small), None, None)
+    assert rc == -2
