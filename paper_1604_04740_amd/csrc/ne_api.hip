@@ -128,7 +128,7 @@ int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t 
         return NE_EINVAL;
     if (n == 0 || N == 0)
         return NE_OK;
-    if (!eps || !Gt || !delta)
+    if (!delta || ((!eps || !Gt) && K > 0))
         return NE_EINVAL;
     const int64_t R = n * p->M;
     if (overlap(eps, R * K * 8, delta, R * N * 8) || overlap(Gt, N * K, delta, R * N * 8))
@@ -260,7 +260,7 @@ int ne_gemm_fused(const int8_t *c, const int8_t *Gt, void *d_hat, int32_t out_dt
         return NE_EINVAL;
     if (n == 0 || N == 0)
         return NE_OK;
-    if (!c || !Gt || !d_hat)
+    if (!d_hat || ((!c || !Gt) && K > 0))
         return NE_EINVAL;
     const int64_t ob = p->M * n * N * out_dtype;
     const int64_t fb = n * ((N + 31) / 32) * 4;
@@ -280,7 +280,7 @@ int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, i
         return NE_EINVAL;
     if (R == 0 || N == 0)
         return NE_OK;
-    if (!A || !Bt || !C)
+    if (!C || ((!A || !Bt) && K > 0))
         return NE_EINVAL;
     if (overlap(A, R * K, C, R * N * 4) || overlap(Bt, N * K, C, R * N * 4))
         return NE_EALIAS;
@@ -297,7 +297,7 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
         return NE_EINVAL;
     if (n == 0 || N == 0)
         return NE_OK;
-    if (!c || !Gt || !d)
+    if (!d || ((!c || !Gt) && K > 0))
         return NE_EINVAL;
     const int64_t ob = (int64_t)M * n * N * 4;
     if (overlap(c, (int64_t)M * n * K, d, ob) || overlap(Gt, N * K, d, ob) ||

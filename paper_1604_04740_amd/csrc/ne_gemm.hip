@@ -38,6 +38,13 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
+#ifndef NE_GEMM_BK
+#define NE_GEMM_BK 64
+#endif
+#ifndef NE_GEMM_STAGES
+#define NE_GEMM_STAGES 4
+#endif
+
 constexpr int kThreads = 256;
 constexpr int BK = 64;
 constexpr int kChunks = BK / 16;
@@ -139,7 +146,8 @@ __global__ __launch_bounds__(kThreads, V::kOcc) void k_gemm(const typename V::Ar
 
     __shared__ __attribute__((aligned(16))) int8_t lds[2 * STAGE];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6); // uniform per wavefront
     const int wm = wave / WN, wn = wave % WN;
     int tm, tn;
     tile_coords(args.tiles_m, args.tiles_n, tm, tn);
@@ -208,6 +216,249 @@ __global__ __launch_bounds__(kThreads, V::kOcc) void k_gemm(const typename V::Ar
     V::epilogue(args, acc, row0, col0, wm, wn, lane);
 }
 
+// ------------------------------------------------- DMA-fed kernel (gfx950)
+//
+// Variants whose A sources are raw int8 rows (PlainV, FusedV) use a ring of
+// S LDS stages filled by buffer_load_dwordx4 ... lds: each instruction moves
+// 64 x 16 bytes from global memory straight into 1 KB of LDS, so no VGPRs are
+// spent on staging and S-1 tiles are in flight.  Each lane picks the global
+// chunk that belongs at its LDS slot under the XOR swizzle.  Out-of-range
+// rows, columns and k read as zero through the buffer descriptor's range
+// check (per-source descriptors start at the tile's first row).  Waits are
+// explicit: before computing tile kt a wavefront waits until only the loads
+// of the tiles after kt are outstanding, then the workgroup barrier makes
+// every wavefront's share of tile kt visible and frees the stage that the
+// next tile is loaded into.
+
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr unsigned kOOB = 0x80000000u;   // beyond every descriptor's range
+constexpr int kRsrcWord3 = 0x00020000;   // raw buffer, 32-bit data format
+
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, int64_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <int BK_>
+__device__ __forceinline__ int swz_off(int row, int chunk)
+{
+    constexpr int C = BK_ / 16;                 // chunks per row
+    constexpr int SH = (C == 4) ? 2 : (C == 8 ? 1 : 0);
+    return row * BK_ + ((chunk ^ ((row >> SH) & (C - 1))) << 4);
+}
+
+// vmcnt-only wait followed by the workgroup barrier (no memory fence: the
+// only outstanding memory operations are this wavefront's LDS DMA loads).
+template <int N>
+__device__ __forceinline__ void wait_vm_barrier()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+// Issue this wavefront's share of the DMA loads of k-tile kt into LDS stage
+// `stage`: regions g = wave, wave + 4, ... of 1 KB; A regions first (source
+// by source), then B.
+template <int NSRC, int BMS, int BN, int BK_, int PART = 0, int NPARTS = 1>
+__device__ __forceinline__ void dma_tile(int8_t *stage, const rsrc_t (&ra)[NSRC], rsrc_t rb,
+                                         int64_t k0, int64_t K, int wave, int lane)
+{
+    constexpr int C = BK_ / 16, RPR = 1024 / BK_, RPS = BMS / RPR; // regions per source
+    constexpr int A_REG = NSRC * RPS, REG = A_REG + BN / RPR;
+    // Region g = 4 * round + wave: with these multiples of four every round is
+    // all-A or all-B and reads one source, so the descriptor is a constant
+    // and the issue has no branches (it can then be interleaved with MFMAs).
+    static_assert(A_REG % 4 == 0 && REG % 4 == 0 && (RPS % 4 == 0 || 4 % RPS == 0),
+                  "DMA region layout");
+    constexpr int ROUNDS = REG / 4;
+    constexpr int PER = (ROUNDS + NPARTS - 1) / NPARTS;
+    const int r_in = lane / C, pc = lane % C;
+#pragma unroll
+    for (int rd = PART * PER; rd < ROUNDS && rd < (PART + 1) * PER; ++rd) {
+        const int g = rd * 4 + wave;
+        const bool isA = rd * 4 < A_REG;                       // same for all waves
+        const int gg = isA ? g : g - A_REG;
+        const int row = (isA ? gg % RPS : gg) * RPR + r_in;
+        const int lc = pc ^ ((row >> (C == 4 ? 2 : 1)) & (C - 1));
+        const int64_t k = k0 + lc * 16;
+        const unsigned off = (k < K) ? (unsigned)(row * K + k) : kOOB;
+        auto *dst = (__attribute__((address_space(3))) void *)(stage + g * 1024);
+        if (isA) {
+            constexpr int dummy = 0;
+            (void)dummy;
+            // source of this round: rd * 4 / RPS when RPS is a multiple of 4,
+            // else every wave of the round reads a different source row-block
+            if constexpr (RPS % 4 == 0) {
+#pragma unroll
+                for (int s2 = 0; s2 < NSRC; ++s2)
+                    if (s2 == rd * 4 / RPS)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra[s2], dst, 16, off, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int s2 = 0; s2 < NSRC; ++s2)
+                    if (s2 == g / RPS)
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(ra[s2], dst, 16, off, 0, 0, 0);
+            }
+        } else {
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, dst, 16, off, 0, 0, 0);
+        }
+    }
+}
+
+// Fragments of one 32-wide k-step: an A fragment per (source, row block)
+// and a B fragment per column block (ds_read_b128 each).
+template <int NSRC, int RB, int CB, int BMS, int BK_, int A_BYTES>
+__device__ __forceinline__ void load_frags(const int8_t *cur, int ks, int wm, int wn, int lane,
+                                           v4i (&a)[NSRC][RB], v4i (&b)[CB])
+{
+    const int chunk = ks * 2 + (lane >> 5);
+#pragma unroll
+    for (int s = 0; s < NSRC; ++s)
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+            const int row = (wm * RB + i) * 32 + (lane & 31);
+            a[s][i] = *(const v4i *)(cur + s * BMS * BK_ + swz_off<BK_>(row, chunk));
+        }
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+        const int row = (wn * CB + j) * 32 + (lane & 31);
+        b[j] = *(const v4i *)(cur + A_BYTES + swz_off<BK_>(row, chunk));
+    }
+}
+
+// Scheduling hint for one k-step: alternate MFMA and LDS read so that the
+// reads of the next k-step are issued in the shadow of this step's MFMAs.
+template <int NMFMA, int NREAD, int NDMA>
+__device__ __forceinline__ void interleave()
+{
+#pragma unroll
+    for (int i = 0; i < NMFMA; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0); // one MFMA
+        if (i < NREAD)
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0); // one LDS read
+        if (i >= NMFMA - NDMA)
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0); // one global->LDS copy
+    }
+    if (NREAD > NMFMA)
+        __builtin_amdgcn_sched_group_barrier(0x100, NREAD - NMFMA, 0);
+}
+
+// k-step ks issues part ks of the next tile's DMA (KS parts in total).
+template <int NSRC, int BMS, int BN, int BK_, int KS>
+__device__ __forceinline__ void dma_part(int ks, int8_t *stage, const rsrc_t (&ra)[NSRC],
+                                         rsrc_t rb, int64_t k0, int64_t K, int wave, int lane)
+{
+    if (ks == 0) dma_tile<NSRC, BMS, BN, BK_, 0, KS>(stage, ra, rb, k0, K, wave, lane);
+    if constexpr (KS > 1) if (ks == 1) dma_tile<NSRC, BMS, BN, BK_, 1, KS>(stage, ra, rb, k0, K, wave, lane);
+    if constexpr (KS > 2) if (ks == 2) dma_tile<NSRC, BMS, BN, BK_, 2, KS>(stage, ra, rb, k0, K, wave, lane);
+    if constexpr (KS > 3) if (ks == 3) dma_tile<NSRC, BMS, BN, BK_, 3, KS>(stage, ra, rb, k0, K, wave, lane);
+}
+
+// Workgroups per CU for the DMA kernel: the variant's register-based target,
+// capped by what its LDS ring leaves room for (160 KB per CU).
+template <class V, int BK_, int S>
+constexpr int dma_occ()
+{
+    constexpr int bytes = S * (V::NSRC * V::BMS * BK_ + V::BN * BK_);
+    constexpr int by_lds = (160 * 1024) / bytes;
+    return V::kOcc < by_lds ? V::kOcc : (by_lds < 1 ? 1 : by_lds);
+}
+
+template <class V, int BK_, int S>
+__global__ __launch_bounds__(kThreads, (dma_occ<V, BK_, S>())) void k_gemm_dma(const typename V::Args args)
+{
+    constexpr int NSRC = V::NSRC, P = V::P, BMS = V::BMS, BN = V::BN, WM = V::WM, WN = V::WN;
+    constexpr int RB = BMS / (32 * WM), CB = BN / (32 * WN);
+    constexpr int RPR = 1024 / BK_;                // rows per 1 KB DMA region
+    constexpr int A_BYTES = NSRC * BMS * BK_;
+    constexpr int STAGE = A_BYTES + BN * BK_;
+    constexpr int A_REG = NSRC * BMS / RPR, B_REG = BN / RPR, REG = A_REG + B_REG;
+    constexpr int LOADS_MIN = REG / 4;             // DMA instructions per tile, fewest over waves
+    static_assert(WM * WN == 4, "four wavefronts");
+    static_assert(BMS % RPR == 0 && BN % RPR == 0, "regions must not straddle sources");
+    static_assert(S >= 2 && S <= 5, "stages");
+
+    __shared__ __attribute__((aligned(1024))) int8_t lds[S * STAGE];
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6); // uniform per wavefront
+    const int wm = wave / WN, wn = wave % WN;
+    int tm, tn;
+    tile_coords(args.tiles_m, args.tiles_n, tm, tn);
+    const int64_t row0 = (int64_t)tm * BMS, col0 = (int64_t)tn * BN;
+    const int64_t K = args.K;
+
+    // One descriptor per A source and one for B, each starting at the tile.
+    rsrc_t ra[NSRC];
+#pragma unroll
+    for (int s = 0; s < NSRC; ++s) {
+        const int64_t rows = V::source_rows(args, s, row0);
+        ra[s] = make_rsrc(V::source_base(args, s, row0), (rows < BMS ? rows : BMS) * K);
+    }
+    const int64_t bcols = args.N - col0;
+    const rsrc_t rb = make_rsrc(args.Bt + col0 * K, (bcols < BN ? bcols : BN) * K);
+
+
+    v16i acc[P][RB][CB];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int i = 0; i < RB; ++i)
+#pragma unroll
+            for (int j = 0; j < CB; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    acc[p][i][j][r] = 0;
+
+    const int nk = (int)((K + BK_ - 1) / BK_);
+    // Prologue: tiles 0 .. S-2.  Every iteration then issues exactly one
+    // tile's loads (past the last tile, range-checked dummies that fill the
+    // free stage with zeros without touching memory), so the number of loads
+    // allowed in flight at each wait is the same constant.
+#pragma unroll
+    for (int t = 0; t < S - 1; ++t)
+        dma_tile<NSRC, BMS, BN, BK_>(lds + t * STAGE, ra, rb, t < nk ? (int64_t)t * BK_ : K, K,
+                                     wave, lane);
+
+    constexpr int KS = BK_ / 32;
+    constexpr int DMA_PER_KS = ((REG + 3) / 4 + KS - 1) / KS; // per wave, per k-step
+    for (int kt = 0; kt < nk; ++kt) {
+        wait_vm_barrier<(S - 2) * LOADS_MIN>();
+        const int tn = kt + S - 1;
+        int8_t *nxt = lds + (tn % S) * STAGE;
+        const int64_t nk0 = tn < nk ? (int64_t)tn * BK_ : K;
+
+        const int8_t *cur = lds + (kt % S) * STAGE;
+        // Fragments of k-step ks+1 are read while the MFMAs of k-step ks
+        // issue (two register sets), one LDS read in the shadow of each MFMA.
+        v4i fa[2][NSRC][RB], fb[2][CB];
+        load_frags<NSRC, RB, CB, BMS, BK_, A_BYTES>(cur, 0, wm, wn, lane, fa[0], fb[0]);
+#pragma unroll
+        for (int ks = 0; ks < BK_ / 32; ++ks) {
+            __builtin_amdgcn_sched_barrier(0); // each k-step is its own scheduling region
+            const int c = ks & 1;
+            if (ks + 1 < BK_ / 32)
+                load_frags<NSRC, RB, CB, BMS, BK_, A_BYTES>(cur, ks + 1, wm, wn, lane, fa[c ^ 1],
+                                                            fb[c ^ 1]);
+            // this k-step's share of the next tile's global -> LDS copies
+            dma_part<NSRC, BMS, BN, BK_, KS>(ks, nxt, ra, rb, nk0, K, wave, lane);
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int i = 0; i < RB; ++i)
+#pragma unroll
+                    for (int j = 0; j < CB; ++j)
+                        acc[p][i][j] = mfma(fa[c][V::src(p)][i], fb[c][j], acc[p][i][j]);
+            if (ks + 1 < BK_ / 32)
+                interleave<P * RB * CB, NSRC * RB + CB, DMA_PER_KS>();
+            else
+                interleave<P * RB * CB, 0, DMA_PER_KS>();
+        }
+    }
+
+    V::epilogue(args, acc, row0, col0, wm, wn, lane);
+}
+
 // Common argument block.
 struct ArgsBase {
     const int8_t *Bt;
@@ -217,8 +468,21 @@ struct ArgsBase {
 
 // ------------------------------------------------------------------ plain
 
+#ifndef NE_PLAIN_BK
+#define NE_PLAIN_BK 128
+#endif
+#ifndef NE_PLAIN_STAGES
+#define NE_PLAIN_STAGES 2
+#endif
+
+// 256 x 256 workgroup tile, each wavefront 128 x 128 (16 accumulator blocks,
+// 256 accumulator registers): half the LDS fragment traffic per MFMA of a
+// 128 x 64 wavefront tile, which is what bounds this loop on gfx950.
 struct PlainV {
-    static constexpr int NSRC = 1, P = 1, BMS = 256, BN = 128, WM = 2, WN = 2, kOcc = 2;
+    static constexpr int NSRC = 1, P = 1, BMS = 256, BN = 256, WM = 2, WN = 2;
+    static constexpr int kOcc = 1;
+    static constexpr bool kDma = true;
+    static constexpr int kBK = NE_PLAIN_BK, kStages = NE_PLAIN_STAGES;
     static constexpr int RB = BMS / (32 * WM), CB = BN / (32 * WN);
     __host__ __device__ static constexpr int src(int) { return 0; }
     struct Args : ArgsBase {
@@ -226,6 +490,14 @@ struct PlainV {
         int32_t *C;
         int64_t R;
     };
+    __device__ __forceinline__ static const int8_t *source_base(const Args &g, int, int64_t row0)
+    {
+        return g.A + row0 * g.K;
+    }
+    __device__ __forceinline__ static int64_t source_rows(const Args &g, int, int64_t row0)
+    {
+        return g.R - row0;
+    }
     template <bool AL> struct AStage {
         static constexpr int CH = BMS * kChunks;
         static constexpr int NA = CH / kThreads;
@@ -273,6 +545,7 @@ template <int L>
 struct EpsV {
     static constexpr int NSRC = L, P = L, BMS = 32, BN = 128, WM = 1, WN = 4;
     static constexpr int kOcc = (L <= 6) ? 2 : 1;
+    static constexpr bool kDma = false;
     static constexpr int RB = 1, CB = 1;
     __host__ __device__ static constexpr int src(int p) { return p; }
     struct Args : ArgsBase {
@@ -339,26 +612,23 @@ struct EpsV {
 
 // ------------------------------------------------------- fused hot path
 
-// Disentangle with a compile-time r: rotate into slot order, extract, rotate back.
-template <int M, int R>
-__device__ __forceinline__ bool extract_r(const int64_t (&d)[M], int l, int64_t (&o)[M])
-{
-    int64_t dr[M], orr[M];
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-        dr[j] = d[(R + j) % M];
-    const bool f = disentangle_rot<M>(dr, l, orr);
-#pragma unroll
-    for (int j = 0; j < M; ++j)
-        o[(R + j) % M] = orr[j];
-    return f;
-}
+#ifndef NE_FUSED_BK
+#define NE_FUSED_BK 128
+#endif
+#ifndef NE_FUSED_STAGES
+#define NE_FUSED_STAGES 3
+#endif
 
+// Workgroup tile: 32 rows of every stream x BN columns; each wavefront owns
+// BN/4 columns of those rows for all M streams and both digits, i.e.
+// 2 * M * (BN / 128) accumulator blocks (at most 256 registers).
 template <int M>
 struct FusedV {
-    static constexpr int NSRC = M, P = 2 * M, BMS = 32, BN = 128, WM = 1, WN = 4;
-    static constexpr int kOcc = (M <= 4) ? 2 : 1;
-    static constexpr int RB = 1, CB = 1;
+    static constexpr int NSRC = M, P = 2 * M, BMS = 32, BN = (M <= 4) ? 256 : 128, WM = 1, WN = 4;
+    static constexpr int kOcc = 1;
+    static constexpr bool kDma = true;
+    static constexpr int kBK = NE_FUSED_BK, kStages = NE_FUSED_STAGES;
+    static constexpr int RB = 1, CB = BN / 128;
     // accumulator set p < M: low digit (c_p) of stream p; p >= M: high digit
     // (c_{p-M-1 mod M}) of stream p - M.
     __host__ __device__ static constexpr int src(int p) { return p < M ? p : (p - 1) % M; }
@@ -374,6 +644,18 @@ struct FusedV {
         int64_t n;
         int l, r, out64;
     };
+    // Slot s holds stream (r + s) mod M, so that the stream the check
+    // rebuilds (r) sits in slot 0 and the epilogue arithmetic is the same for
+    // every r.
+    __device__ __forceinline__ static int stream_of(const Args &g, int s) { return (g.r + s) % M; }
+    __device__ __forceinline__ static const int8_t *source_base(const Args &g, int s, int64_t row0)
+    {
+        return g.c + ((int64_t)stream_of(g, s) * g.n + row0) * g.K;
+    }
+    __device__ __forceinline__ static int64_t source_rows(const Args &g, int, int64_t row0)
+    {
+        return g.n - row0;
+    }
     template <bool AL> struct AStage {
         static constexpr int CH = M * BMS * kChunks;
         static constexpr int NA = (CH + kThreads - 1) / kThreads;
@@ -385,7 +667,7 @@ struct FusedV {
                 const int q = tid + i * kThreads;
                 const int s = q / (BMS * kChunks), rem = q % (BMS * kChunks);
                 const int64_t row = row0 + rem / kChunks;
-                a[i] = (q < CH) ? load_chunk<AL>(g.c + ((int64_t)s * g.n + row) * g.K,
+                a[i] = (q < CH) ? load_chunk<AL>(g.c + ((int64_t)stream_of(g, s) * g.n + row) * g.K,
                                                  k0 + (rem % kChunks) * 16, g.K, row < g.n)
                                 : v4i{0, 0, 0, 0};
             }
@@ -403,69 +685,61 @@ struct FusedV {
         }
     };
 
-    template <int R>
     __device__ __forceinline__ static void epi(const Args &g, v16i (&acc)[P][RB][CB],
                                                int64_t row0, int64_t col0, int wm, int wn,
                                                int lane, int64_t f_beg, int64_t f_end)
     {
         const int64_t W = (g.N + 31) / 32;
-        const int64_t col = col0 + wn * 32 + acc_col(lane);
-        const int64_t word = (col0 + wn * 32) / 32;
         unsigned long long cnt = 0;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int64_t row = row0 + wm * 32 + acc_row(r, lane);
-            const bool valid = row < g.n && col < g.N;
-            int64_t d[M], o[M];
+        for (int j = 0; j < CB; ++j) {
+            const int64_t cblk = col0 + (wn * CB + j) * 32;
+            const int64_t col = cblk + acc_col(lane);
+            const int64_t word = cblk / 32;
 #pragma unroll
-            for (int s = 0; s < M; ++s)
-                d[s] = (int64_t)((uint64_t)(int64_t)acc[s][0][0][r] +
-                                 ((uint64_t)(int64_t)acc[M + s][0][0][r] << g.l));
-            for (int64_t f = f_beg; f < f_end; ++f) {
-                if (g.inj_pos[f] == row * g.N + col) {
-                    const int st = g.inj_stream[f];
-                    const uint64_t msk = g.inj_mask[f];
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * 32 + acc_row(r, lane);
+                const bool valid = row < g.n && col < g.N;
+                int64_t d[M], o[M];
 #pragma unroll
-                    for (int s = 0; s < M; ++s)
-                        if (s == st)
-                            d[s] = (int64_t)((uint64_t)d[s] ^ msk);
+                for (int s = 0; s < M; ++s)
+                    d[s] = (int64_t)((uint64_t)(int64_t)acc[s][0][j][r] +
+                                     ((uint64_t)(int64_t)acc[M + s][0][j][r] << g.l));
+                for (int64_t f = f_beg; f < f_end; ++f) {
+                    if (g.inj_pos[f] == row * g.N + col) {
+                        const int st = (g.inj_stream[f] - g.r + M) % M; // its slot
+                        const uint64_t msk = g.inj_mask[f];
+#pragma unroll
+                        for (int s = 0; s < M; ++s)
+                            if (s == st)
+                                d[s] = (int64_t)((uint64_t)d[s] ^ msk);
+                    }
                 }
-            }
-            const bool flag = extract_r<M, R>(d, g.l, o) && valid;
-            if (valid) {
-                if (g.out64) {
+                const bool flag = disentangle_rot<M>(d, g.l, o) && valid;
+                if (valid) {
+                    if (g.out64) {
 #pragma unroll
-                    for (int s = 0; s < M; ++s)
-                        ((int64_t *)g.dhat)[((int64_t)s * g.n + row) * g.N + col] = o[s];
-                } else {
+                        for (int s = 0; s < M; ++s)
+                            ((int64_t *)g.dhat)[((int64_t)stream_of(g, s) * g.n + row) * g.N + col] =
+                                o[s];
+                    } else {
 #pragma unroll
-                    for (int s = 0; s < M; ++s)
-                        ((int32_t *)g.dhat)[((int64_t)s * g.n + row) * g.N + col] = (int32_t)o[s];
+                        for (int s = 0; s < M; ++s)
+                            ((int32_t *)g.dhat)[((int64_t)stream_of(g, s) * g.n + row) * g.N + col] =
+                                (int32_t)o[s];
+                    }
                 }
+                const uint64_t mask = __ballot(flag);
+                if (g.flags && word < W && row < g.n && (lane & 31) == 0)
+                    g.flags[row * W + word] = (uint32_t)(lane ? (mask >> 32) : mask);
+                cnt += (unsigned long long)__popcll(mask);
+                // one output position at a time: keeps the 2M words of a
+                // position, not of all positions, live in registers
+                __builtin_amdgcn_sched_barrier(0);
             }
-            const uint64_t mask = __ballot(flag);
-            if (g.flags && word < W && row < g.n && (lane & 31) == 0)
-                g.flags[row * W + word] = (uint32_t)(lane ? (mask >> 32) : mask);
-            cnt += (unsigned long long)__popcll(mask);
         }
         if (g.n_bad && lane == 0 && cnt)
             atomicAdd(g.n_bad, cnt);
-    }
-
-    template <int R>
-    __device__ __forceinline__ static void epi_dispatch(int r, const Args &g,
-                                                        v16i (&acc)[P][RB][CB], int64_t row0,
-                                                        int64_t col0, int wm, int wn, int lane,
-                                                        int64_t fb, int64_t fe)
-    {
-        if constexpr (R == M - 1) {
-            epi<R>(g, acc, row0, col0, wm, wn, lane, fb, fe);
-        } else {
-            if (r == R)
-                epi<R>(g, acc, row0, col0, wm, wn, lane, fb, fe);
-            else
-                epi_dispatch<R + 1>(r, g, acc, row0, col0, wm, wn, lane, fb, fe);
-        }
     }
 
     __device__ __forceinline__ static void epilogue(const Args &g, v16i (&acc)[P][RB][CB],
@@ -491,7 +765,7 @@ struct FusedV {
             }
             fe = lo;
         }
-        epi_dispatch<0>(g.r, g, acc, row0, col0, wm, wn, lane, fb, fe);
+        epi(g, acc, row0, col0, wm, wn, lane, fb, fe);
     }
 };
 
@@ -501,6 +775,7 @@ template <int M>
 struct AbftV {
     static constexpr int NSRC = M + 2, P = M + 2, BMS = 32, BN = 128, WM = 1, WN = 4;
     static constexpr int kOcc = (M <= 6) ? 2 : 1;
+    static constexpr bool kDma = false;
     static constexpr int RB = 1, CB = 1;
     __host__ __device__ static constexpr int src(int p) { return p; }
     struct Args : ArgsBase {
@@ -596,6 +871,12 @@ int launch(typename V::Args &args, int64_t rows, bool al, hipStream_t s)
     args.tiles_m = (int)tm;
     args.tiles_n = (int)tn;
     const dim3 grid((unsigned)(tm * tn));
+    if constexpr (V::kDma) {
+        if (al) {
+            k_gemm_dma<V, V::kBK, V::kStages><<<grid, kThreads, 0, s>>>(args);
+            return launch_status();
+        }
+    }
     if (al)
         k_gemm<V, true><<<grid, kThreads, 0, s>>>(args);
     else
