@@ -12,8 +12,9 @@
  * General conventions (every entry point):
  *   - Pointers named as device pointers must point to device memory of the
  *     current HIP device (any allocator; 16-byte aligned where stated).
- *     The caller owns every buffer; the library allocates nothing and keeps
- *     no global state.
+ *     The caller owns every buffer; the library allocates no device memory
+ *     and keeps no global state (the batch planner's small host-side plan
+ *     object is the one allocation, released by ne_batch_free).
  *   - Streams are stored stream-major: element n of stream m is at
  *     [m * N + n] (N = elements per stream); matrices are row-major.
  *   - Words are w = 64-bit two's complement (int64).  Every word operation
@@ -127,7 +128,8 @@ int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t 
  *   eps       device, [M][N] int64;  eps_bits as for ne_lsb_gemm.
  *   g         device, [N] int8.
  *   delta     device, [M][N] int64; must not overlap eps.
- *   N         1 .. 131071 (exact int32 digit accumulation).
+ *   N         1 .. 131071.  Evaluated directly with 64-bit multiply-adds
+ *             (the operation is latency-bound at these lengths).
  */
 int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
                     int64_t N, const ne_params_t *p, ne_stream_t stream);
@@ -238,6 +240,123 @@ int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, i
 int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *flags,
                     unsigned long long *n_bad, int32_t M, int64_t n, int64_t K, int64_t N,
                     ne_stream_t stream);
+
+/*
+ * Fused circular convolution, one launch: entangle in the staging of each
+ * kernel tile, the star operator of section II on the entangled words, then
+ * disentangle and check (section III-C).  delta never reaches memory.
+ *   c         device, [M][N] of c_dtype (NE_I8, NE_I32 or NE_I64).
+ *   c_bits    bound on the inputs: |c| < 2^(c_bits-1); with |g| <= 128 it
+ *             gives the a-priori bound N * 2^(c_bits-1) * 128, which must not
+ *             exceed D (section III-C), else NE_ERANGE.
+ *   g         device, [N] int8.
+ *   d_hat     device, [M][N] of out_dtype (NE_I32 keeps the low 32 bits).
+ *   flags     device, [ceil(N/32)] uint32 bitmask, or NULL.
+ *   n_bad     device counter (incremented), or NULL.
+ *   N         1 .. 131071.
+ */
+int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g,
+                      void *d_hat, int32_t out_dtype, uint32_t *flags,
+                      unsigned long long *n_bad, int64_t N, const ne_params_t *p,
+                      ne_stream_t stream);
+
+/*
+ * Fused permutation + scaling + addition, one launch (section II, op in
+ * {permutation, x, +}, with the constant self-entangled per the footnote of
+ * section III-A): for every position n the M inputs at perm[n] are
+ * entangled, delta = scale[n] eps + (2^l + 1) add[n], then disentangled and
+ * checked.  The caller guarantees |scale[n] c + add[n]| <= D (the range of
+ * section III-C); it is not checked a priori.
+ *   c          device, [M][N] of c_dtype;  perm device [N] int32 (clamped);
+ *   scale/add  device [N] int64 or NULL;   d_hat device [M][N] out_dtype;
+ *   flags      device [ceil(N/32)] or NULL; n_bad device counter or NULL.
+ */
+int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
+                           const int64_t *scale, const int64_t *add, void *d_hat,
+                           int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
+                           int64_t N, const ne_params_t *p, ne_stream_t stream);
+
+/* ------------------------------------------------------------------ batch */
+
+#define NE_OP_GEMM 0
+#define NE_OP_CONV 1
+#define NE_OP_PERM 2
+
+/*
+ * One independent problem of a batch.  Parameters (l, k) follow the rule of
+ * ne_params_default for its M (3..8, w = 64); r_check picks the check stream.
+ *   NE_OP_GEMM: c [M][n][K] int8 (16-byte aligned, K % 16 == 0), g = Gt
+ *               [N][K] int8; d_hat [M][n][N]; flags row-padded
+ *               [n][ceil(N/32)] as in ne_gemm_fused.
+ *   NE_OP_CONV: c [M][N] int8, g [N] int8 (circular convolution); d_hat
+ *               [M][N]; flags [ceil(N/32)].
+ *   NE_OP_PERM: c [M][N] int8, perm [N] int32, scale / add [N] int64 or
+ *               NULL; d_hat [M][N]; flags [ceil(N/32)].
+ * All pointers are device pointers; flags and n_bad may be NULL.
+ */
+typedef struct ne_problem {
+    int32_t op, M, r_check, out_dtype;
+    int64_t n, K, N;
+    const void *c;
+    const void *g;
+    const int32_t *perm;
+    const int64_t *scale;
+    const int64_t *add;
+    void *d_hat;
+    uint32_t *flags;
+    unsigned long long *n_bad;
+} ne_problem_t;
+
+/*
+ * Per-bucket choices, indexed [M - 3][size class]; size class 0: largest
+ * dimension <= 256, 1: <= 1024, 2: larger.  gemm_bn is the output-tile width
+ * of a GEMM work item (128, or 256 for M <= 4); perm_chunk the number of
+ * positions of a permute/scale work item (a multiple of 64).
+ */
+typedef struct ne_batch_tuning {
+    int32_t gemm_bn[6][3];
+    int64_t perm_chunk[6][3];
+} ne_batch_tuning_t;
+
+typedef struct ne_batch ne_batch_t; /* opaque host-side plan */
+
+/*
+ * Plan a batch: validates every problem, splits it into work items (GEMM
+ * output tiles, 256-position convolution blocks, permute/scale chunks),
+ * orders them longest-first and writes problem table + items into the
+ * caller's device buffer table_dev (256-byte aligned, table_bytes long; it
+ * must not be in use by a pending run).  With table_dev == NULL only
+ * *table_needed is set.  tuning may be NULL (defaults).  On success *plan is
+ * a small host object (the only thing the library allocates; free it with
+ * ne_batch_free).  Setup call: blocking, not for graph capture.
+ */
+int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tuning_t *tuning,
+                  void *table_dev, int64_t table_bytes, int64_t *table_needed,
+                  ne_batch_t **plan);
+
+/*
+ * Run a planned batch: one persistent launch (one workgroup per compute
+ * unit) preceded by a one-thread counter reset.  Both are kernels, so the
+ * call can be captured into a HIP graph and replayed.  Runs on one stream
+ * must not overlap (they share the table's work counter).
+ */
+int ne_batch_run(const ne_batch_t *plan, ne_stream_t stream);
+
+/* Number of work items of a plan (-1 for NULL). */
+int ne_batch_items(const ne_batch_t *plan);
+
+void ne_batch_free(ne_batch_t *plan);
+
+/*
+ * Autotuner: for every (operation, M, size class) bucket present in the
+ * problem list, plans and times (reps runs, HIP events) each candidate of
+ * that bucket on the device and keeps the fastest in *out (other buckets get
+ * defaults).  Runs the problems (overwriting their outputs) and uses
+ * table_dev as scratch for the plans.  Blocking.
+ */
+int ne_batch_autotune(const ne_problem_t *problems, int32_t count, void *table_dev,
+                      int64_t table_bytes, int32_t reps, ne_batch_tuning_t *out,
+                      ne_stream_t stream);
 
 #ifdef __cplusplus
 }

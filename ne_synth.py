@@ -111,3 +111,45 @@ def bit_flip_trials(seed: int, trials: int, M: int, positions: int, w: int = 64)
     pos = uniform_int(seed, 12, (trials,), 0, positions)
     bit = uniform_int(seed, 13, (trials,), 0, w)
     return stream, pos, bit
+
+
+def batch_recipe(seed: int, count: int = 256, s_min: int = 64, s_max: int = 2048,
+                 kinds=(0.6, 0.3, 0.1)):
+    """Mixed batch of independent problems: M uniform in {3..8}; size
+    s = round(s_min * (s_max / s_min) ** u), u uniform in [0, 1); operation
+    GEMM / circular convolution / permute+scale with probabilities `kinds`;
+    values uniform in [-128, 128).  GEMM: M streams s x K times a shared
+    K x s operand, K = s rounded up to a multiple of 16.  Convolution: M
+    streams and a filter of length s.  Permute+scale: s * s positions with a
+    uniform random permutation (the SplitMix64 Fisher-Yates shuffle up to
+    200000 positions, numpy's seeded generator above that, for speed),
+    scale and add uniform in [-128, 128).
+    Returns a list of dicts of host arrays (int8 inputs, int64 scale/add)."""
+    M = uniform_int(seed, 31, (count,), 3, 9)
+    u = uniform_int(seed, 32, (count,), 0, 1 << 30).astype(np.float64) / float(1 << 30)
+    size = np.rint(s_min * (s_max / s_min) ** u).astype(np.int64)
+    kind_u = uniform_int(seed, 33, (count,), 0, 1000)
+    edges = np.cumsum(np.array(kinds) * 1000).astype(np.int64)
+    out = []
+    for i in range(count):
+        k = int(np.searchsorted(edges, kind_u[i], side="right"))
+        m, s = int(M[i]), int(size[i])
+        sub = seed * 1009 + i
+        if k == 0:
+            K = (s + 15) // 16 * 16
+            c = uniform_int(sub, 1, (m, s, K), -128, 128, dtype=np.int8)
+            G = uniform_int(sub, 2, (K, s), -128, 128, dtype=np.int8)
+            out.append(dict(op=0, M=m, c=c, G=G))
+        elif k == 1:
+            c = uniform_int(sub, 3, (m, s), -128, 128, dtype=np.int8)
+            g = uniform_int(sub, 4, (s,), -128, 128, dtype=np.int8)
+            out.append(dict(op=1, M=m, c=c, g=g))
+        else:
+            n = s * s
+            c = uniform_int(sub, 5, (m, n), -128, 128, dtype=np.int8)
+            perm = np.random.default_rng(sub).permutation(n).astype(np.int32) if n > 200000 \
+                else permutation(sub, 6, n).astype(np.int32)
+            scale = uniform_int(sub, 7, (n,), -128, 128)
+            add = uniform_int(sub, 8, (n,), -128, 128)
+            out.append(dict(op=2, M=m, c=c, perm=perm, scale=scale, add=add))
+    return out

@@ -20,7 +20,8 @@ __all__ = [
     "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
-    "Inject",
+    "ne_circconv_fused", "ne_permute_scale_fused", "Inject", "Problem", "Batch", "ne_batch_plan",
+    "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -42,6 +43,21 @@ class Params(ctypes.Structure):
 
     def __repr__(self):
         return f"Params(M={self.M}, w={self.w}, l={self.l}, k={self.k}, r_check={self.r_check})"
+
+
+NE_OP_GEMM, NE_OP_CONV, NE_OP_PERM = 0, 1, 2
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("M", ctypes.c_int32), ("r_check", ctypes.c_int32),
+                ("out_dtype", ctypes.c_int32), ("n", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("N", ctypes.c_int64), ("c", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("perm", ctypes.c_void_p), ("scale", ctypes.c_void_p), ("add", ctypes.c_void_p),
+                ("d_hat", ctypes.c_void_p), ("flags", ctypes.c_void_p), ("n_bad", ctypes.c_void_p)]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("gemm_bn", (ctypes.c_int32 * 3) * 6), ("perm_chunk", (ctypes.c_int64 * 3) * 6)]
 
 
 class _Inject(ctypes.Structure):
@@ -77,6 +93,17 @@ def lib():
             "ne_plain_gemm_i8": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp], ctypes.c_int),
             "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp],
                                 ctypes.c_int),
+            "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp],
+                                  ctypes.c_int),
+            "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
+                                        _vp], ctypes.c_int),
+            "ne_batch_plan": ([ctypes.POINTER(_Problem), _i32, ctypes.POINTER(_Tuning), _vp, _i64,
+                               ctypes.POINTER(_i64), ctypes.POINTER(_vp)], ctypes.c_int),
+            "ne_batch_run": ([_vp, _vp], ctypes.c_int),
+            "ne_batch_items": ([_vp], ctypes.c_int),
+            "ne_batch_free": ([_vp], None),
+            "ne_batch_autotune": ([ctypes.POINTER(_Problem), _i32, _vp, _i64, _i32,
+                                   ctypes.POINTER(_Tuning), _vp], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(L, name)
@@ -322,3 +349,157 @@ def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None 
         "ne_abft_gemm_i8")
     return out, flags, n_bad
 
+
+
+# ----------------------------------------------------------- fused conv/perm
+
+def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
+                      out_dtype=torch.int64, out: torch.Tensor | None = None,
+                      flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+    """c: [M, N] int8/int32/int64, g: [N] int8 -> (d_hat [M, N], flags [ceil(N/32)], n_bad)."""
+    M, N = c.shape
+    if M != p.M or g.shape != (N,):
+        raise ValueError("shape mismatch")
+    if c.dtype not in _DT:
+        raise TypeError("c must be int8, int32 or int64")
+    if out is None:
+        out = torch.empty((M, N), dtype=out_dtype, device=c.device)
+    if flags is True:
+        flags = torch.empty(((N + 31) // 32,), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    _ok(lib().ne_circconv_fused(_dev(c, "c"), _DT[c.dtype], c_bits, _dev(g, "g", torch.int8),
+                                _dev(out, "out", out_dtype), _DT[out_dtype],
+                                _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
+                                N, ctypes.byref(p), _stream()), "ne_circconv_fused")
+    return out, flags, n_bad
+
+
+def ne_permute_scale_fused(c: torch.Tensor, perm: torch.Tensor, scale: torch.Tensor | None,
+                           add: torch.Tensor | None, p: Params, out_dtype=torch.int64,
+                           out: torch.Tensor | None = None, flags: bool | torch.Tensor = True,
+                           n_bad: torch.Tensor | None = None):
+    """c: [M, N]; perm [N] int32; scale/add [N] int64 or None -> (d_hat, flags, n_bad)."""
+    M, N = c.shape
+    if M != p.M or perm.shape != (N,):
+        raise ValueError("shape mismatch")
+    if c.dtype not in _DT:
+        raise TypeError("c must be int8, int32 or int64")
+    if out is None:
+        out = torch.empty((M, N), dtype=out_dtype, device=c.device)
+    if flags is True:
+        flags = torch.empty(((N + 31) // 32,), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    _ok(lib().ne_permute_scale_fused(_dev(c, "c"), _DT[c.dtype], _dev(perm, "perm", torch.int32),
+                                     _opt(scale, "scale", torch.int64), _opt(add, "add", torch.int64),
+                                     _dev(out, "out", out_dtype), _DT[out_dtype],
+                                     _opt(flags, "flags", torch.int32),
+                                     _dev(n_bad, "n_bad", torch.int64), N, ctypes.byref(p),
+                                     _stream()), "ne_permute_scale_fused")
+    return out, flags, n_bad
+
+
+# -------------------------------------------------------------------- batch
+
+class Problem:
+    """One problem of a batch (see ne_problem_t in include/ne.h); keeps its
+    tensors alive.  Outputs (d_hat, flags, n_bad) are allocated here."""
+
+    def __init__(self, op: int, c: torch.Tensor, g: torch.Tensor | None = None, *,
+                 perm: torch.Tensor | None = None, scale: torch.Tensor | None = None,
+                 add: torch.Tensor | None = None, r_check: int = 0, out_dtype=torch.int32):
+        self.op, self.c, self.g, self.perm, self.scale, self.add = op, c, g, perm, scale, add
+        self.M = c.shape[0]
+        dev = c.device
+        if op == NE_OP_GEMM:
+            self.n, self.K = c.shape[1], c.shape[2]
+            self.N = g.shape[0]
+            self.d_hat = torch.empty((self.M, self.n, self.N), dtype=out_dtype, device=dev)
+            self.flags = torch.empty((self.n, (self.N + 31) // 32), dtype=torch.int32, device=dev)
+        else:
+            self.n, self.K, self.N = 1, 1, c.shape[1]
+            self.d_hat = torch.empty((self.M, self.N), dtype=out_dtype, device=dev)
+            self.flags = torch.empty(((self.N + 31) // 32,), dtype=torch.int32, device=dev)
+        self.n_bad = torch.zeros((1,), dtype=torch.int64, device=dev)
+        self.r_check, self.out_dtype = r_check, out_dtype
+
+    def struct(self) -> _Problem:
+        s = _Problem()
+        s.op, s.M, s.r_check, s.out_dtype = self.op, self.M, self.r_check, _DT[self.out_dtype]
+        s.n, s.K, s.N = self.n, self.K, self.N
+        s.c = _dev(self.c, "c", torch.int8)
+        s.g = _dev(self.g, "g", torch.int8) if self.g is not None else None
+        s.perm = _opt(self.perm, "perm", torch.int32)
+        s.scale = _opt(self.scale, "scale", torch.int64)
+        s.add = _opt(self.add, "add", torch.int64)
+        s.d_hat = _dev(self.d_hat, "d_hat", self.out_dtype)
+        s.flags = _dev(self.flags, "flags", torch.int32)
+        s.n_bad = _dev(self.n_bad, "n_bad", torch.int64)
+        return s
+
+
+def _problem_array(problems):
+    arr = (_Problem * len(problems))()
+    for i, q in enumerate(problems):
+        arr[i] = q.struct()
+    return arr
+
+
+class Batch:
+    """A planned batch: owns the device table and the library's host plan."""
+
+    def __init__(self, problems, tuning=None):
+        self.problems = list(problems)
+        self._arr = _problem_array(self.problems)
+        need = _i64()
+        t = ctypes.byref(tuning) if tuning is not None else None
+        _ok(lib().ne_batch_plan(self._arr, len(self.problems), t, None, 0, ctypes.byref(need),
+                                None), "ne_batch_plan")
+        dev = self.problems[0].c.device if self.problems else torch.device("cuda")
+        self.table = torch.empty((max(need.value, 256),), dtype=torch.uint8, device=dev)
+        plan = _vp()
+        _ok(lib().ne_batch_plan(self._arr, len(self.problems), t, _dev(self.table, "table"),
+                                self.table.numel(), ctypes.byref(need), ctypes.byref(plan)),
+            "ne_batch_plan")
+        self._plan = plan
+
+    @property
+    def items(self) -> int:
+        return lib().ne_batch_items(self._plan)
+
+    def run(self):
+        _ok(lib().ne_batch_run(self._plan, _stream()), "ne_batch_run")
+
+    def __del__(self):
+        try:
+            if getattr(self, "_plan", None):
+                lib().ne_batch_free(self._plan)
+                self._plan = None
+        except Exception:
+            pass
+
+
+def ne_batch_plan(problems, tuning=None) -> Batch:
+    return Batch(problems, tuning)
+
+
+def ne_batch_run(batch: Batch):
+    batch.run()
+
+
+def ne_batch_autotune(problems, reps: int = 3) -> _Tuning:
+    """Time every bucket's candidates on the device; returns the tuning struct."""
+    arr = _problem_array(problems)
+    need = _i64()
+    _ok(lib().ne_batch_plan(arr, len(problems), None, None, 0, ctypes.byref(need), None),
+        "ne_batch_plan")
+    table = torch.empty((max(need.value, 256),), dtype=torch.uint8, device=problems[0].c.device)
+    out = _Tuning()
+    _ok(lib().ne_batch_autotune(arr, len(problems), _dev(table, "table"), table.numel(), reps,
+                                ctypes.byref(out), _stream()), "ne_batch_autotune")
+    return out

@@ -308,4 +308,62 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
     return launch_gemm_abft(c, Gt, d, flags, n_bad, n, K, N, M, hs(stream));
 }
 
+int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g,
+                      void *d_hat, int32_t out_dtype, uint32_t *flags,
+                      unsigned long long *n_bad, int64_t N, const ne_params_t *p,
+                      ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsFused);
+    if (rc)
+        return rc;
+    if (N < 0 || N > kMaxK || (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64) ||
+        (out_dtype != NE_I32 && out_dtype != NE_I64) || c_bits < 1 || c_bits > 8 * c_dtype)
+        return NE_EINVAL;
+    int64_t D = 0;
+    ne_range_bound(p, &D);
+    if (N == 0)
+        return NE_OK;
+    // a-priori bound N * 2^(c_bits-1) * 128 <= D, compared without overflow
+    if (c_bits - 1 + 7 >= 63 || N > (D >> (c_bits - 1 + 7)))
+        return NE_ERANGE;
+    if (!c || !g || !d_hat)
+        return NE_EINVAL;
+    const int64_t ob = N * p->M * out_dtype;
+    if (overlap(c, N * p->M * c_dtype, d_hat, ob) || overlap(g, N, d_hat, ob) ||
+        overlap(flags, ((N + 31) / 32) * 4, d_hat, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 ||
+        (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_circconv_fused(c, c_dtype, g, d_hat, out_dtype == NE_I64, flags, n_bad, N, p->M,
+                                 p->l, p->r_check, hs(stream));
+}
+
+int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
+                           const int64_t *scale, const int64_t *add, void *d_hat,
+                           int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
+                           int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (N < 0 || N > 0x7fffffff || (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64) ||
+        (out_dtype != NE_I32 && out_dtype != NE_I64))
+        return NE_EINVAL;
+    if (N == 0)
+        return NE_OK;
+    if (!c || !perm || !d_hat)
+        return NE_EINVAL;
+    const int64_t ob = N * p->M * out_dtype;
+    if (overlap(c, N * p->M * c_dtype, d_hat, ob) || overlap(perm, N * 4, d_hat, ob) ||
+        overlap(scale, N * 8, d_hat, ob) || overlap(add, N * 8, d_hat, ob) ||
+        overlap(flags, ((N + 31) / 32) * 4, d_hat, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)perm % 4 ||
+        (uintptr_t)scale % 8 || (uintptr_t)add % 8 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_permute_scale_fused(c, c_dtype, perm, scale, add, d_hat, out_dtype == NE_I64,
+                                      flags, n_bad, N, p->M, p->l, p->r_check, hs(stream));
+}
+
 } // extern "C"

@@ -1,0 +1,501 @@
+// ne_batch.hip -- many independent entangled problems (uneven M, size and
+// operation) in one persistent launch.
+//
+// Host side (setup, not graph-capturable): ne_batch_plan turns a problem
+// list into work items -- one per GEMM output tile, one per 256-position
+// convolution block, one per permute/scale chunk -- orders them
+// longest-first by a cost estimate (so the long items start early and the
+// short ones fill the tail), and writes the problem table and item list
+// into a caller-provided device buffer.  ne_batch_autotune times the
+// candidate tile choices of every (operation, M, size-class) bucket on the
+// device and returns the fastest per bucket.
+//
+// Device side: ne_batch_run launches a counter reset and the persistent
+// kernel (grid = one workgroup per CU).  Every workgroup takes the next item
+// from a global atomic counter and runs the fused tile function of that
+// item's operation; it exits when the counter passes the item count, so the
+// grid always drains.  Both launches are plain kernels (no memset nodes),
+// so ne_batch_run can be captured in a HIP graph and replayed.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "ne_conv_impl.h"
+#include "ne_gemm_impl.h"
+#include "ne_perm_impl.h"
+
+namespace ne {
+namespace {
+
+constexpr int kBatchThreads = 256;
+constexpr int kGemmBK = NE_FUSED_BK;
+constexpr int kGemmStages = NE_FUSED_STAGES;
+
+struct DevProblem {
+    int32_t op, M, l, r;
+    int32_t out64, bn, tiles_m, tiles_n;
+    int64_t n, K, N, chunk;
+    const void *c;
+    const void *g;
+    const int32_t *perm;
+    const int64_t *scale;
+    const int64_t *add;
+    void *dhat;
+    uint32_t *flags;
+    unsigned long long *n_bad;
+};
+
+struct DevItem {
+    int32_t problem, a, b, pad;
+};
+
+struct DevHeader {
+    unsigned int counter;
+    int32_t n_items, n_problems, pad;
+    int64_t problems_off, items_off;
+};
+
+constexpr int64_t kHeaderBytes = 256;
+
+template <int M, int BN>
+__device__ __forceinline__ void run_gemm_tile(const DevProblem &P, int tm, int tn, int8_t *lds)
+{
+    using V = FusedV<M, BN>;
+    typename V::Args a{};
+    a.Bt = (const int8_t *)P.g;
+    a.K = P.K;
+    a.N = P.N;
+    a.tiles_m = P.tiles_m;
+    a.tiles_n = P.tiles_n;
+    a.c = (const int8_t *)P.c;
+    a.dhat = P.dhat;
+    a.flags = P.flags;
+    a.n_bad = P.n_bad;
+    a.n = P.n;
+    a.l = P.l;
+    a.r = P.r;
+    a.out64 = P.out64;
+    gemm_tile_dma<V, kGemmBK, kGemmStages>(a, tm, tn, lds);
+}
+
+__device__ __forceinline__ void run_gemm(const DevProblem &P, int tm, int tn, int8_t *lds)
+{
+    if (P.bn == 256) {
+        switch (P.M) {
+        case 3: run_gemm_tile<3, 256>(P, tm, tn, lds); return;
+        case 4: run_gemm_tile<4, 256>(P, tm, tn, lds); return;
+        default: return;
+        }
+    }
+    switch (P.M) {
+    case 3: run_gemm_tile<3, 128>(P, tm, tn, lds); return;
+    case 4: run_gemm_tile<4, 128>(P, tm, tn, lds); return;
+    case 5: run_gemm_tile<5, 128>(P, tm, tn, lds); return;
+    case 6: run_gemm_tile<6, 128>(P, tm, tn, lds); return;
+    case 7: run_gemm_tile<7, 128>(P, tm, tn, lds); return;
+    case 8: run_gemm_tile<8, 128>(P, tm, tn, lds); return;
+    default: return;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void run_conv_m(const DevProblem &P, int block, int8_t *lds)
+{
+    auto *xs = (int64_t(*)[2 * kConvT])lds;
+    auto *gs = (int32_t *)(lds + (size_t)M * 2 * kConvT * sizeof(int64_t));
+    conv_fused_block<M, int8_t>((const int8_t *)P.c, (const int8_t *)P.g, P.dhat, P.out64,
+                                P.flags, P.n_bad, P.N, P.l, P.r, (int64_t)block * kConvT, xs, gs);
+}
+
+__device__ __forceinline__ void run_conv(const DevProblem &P, int block, int8_t *lds)
+{
+    switch (P.M) {
+    case 3: run_conv_m<3>(P, block, lds); return;
+    case 4: run_conv_m<4>(P, block, lds); return;
+    case 5: run_conv_m<5>(P, block, lds); return;
+    case 6: run_conv_m<6>(P, block, lds); return;
+    case 7: run_conv_m<7>(P, block, lds); return;
+    case 8: run_conv_m<8>(P, block, lds); return;
+    default: return;
+    }
+}
+
+template <int M>
+__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk)
+{
+    const int64_t first = (int64_t)chunk * P.chunk;
+    const int64_t last = first + P.chunk < P.N ? first + P.chunk : P.N;
+    perm_fused_range<M, int8_t>((const int8_t *)P.c, P.perm, P.scale, P.add, P.dhat, P.out64,
+                                P.flags, P.n_bad, P.N, P.l, P.r, first, last, 0, kBatchThreads);
+}
+
+__device__ __forceinline__ void run_perm(const DevProblem &P, int chunk)
+{
+    switch (P.M) {
+    case 3: run_perm_m<3>(P, chunk); return;
+    case 4: run_perm_m<4>(P, chunk); return;
+    case 5: run_perm_m<5>(P, chunk); return;
+    case 6: run_perm_m<6>(P, chunk); return;
+    case 7: run_perm_m<7>(P, chunk); return;
+    case 8: run_perm_m<8>(P, chunk); return;
+    default: return;
+    }
+}
+
+constexpr int kBatchLds = 3 * 49152; // largest GEMM ring (M = 4, BN = 256 / M = 8, BN = 128)
+static_assert(dma_lds_bytes<FusedV<4, 256>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
+static_assert(dma_lds_bytes<FusedV<8, 128>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
+
+__global__ void k_batch_reset(DevHeader *h) { h->counter = 0u; }
+
+__global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table)
+{
+    __shared__ __attribute__((aligned(1024))) int8_t lds[kBatchLds];
+    __shared__ int item_sh;
+    auto *h = (DevHeader *)table;
+    const auto *problems = (const DevProblem *)(table + h->problems_off);
+    const auto *items = (const DevItem *)(table + h->items_off);
+    const int n_items = h->n_items;
+    for (;;) {
+        if (threadIdx.x == 0)
+            item_sh = (int)atomicAdd(&h->counter, 1u);
+        __syncthreads();
+        const int it = item_sh;
+        __syncthreads();
+        if (it >= n_items)
+            break;
+        const DevItem im = items[it];
+        const DevProblem &P = problems[im.problem];
+        if (P.op == NE_OP_GEMM)
+            run_gemm(P, im.a, im.b, lds);
+        else if (P.op == NE_OP_CONV)
+            run_conv(P, im.a, lds);
+        else
+            run_perm(P, im.a);
+        __syncthreads(); // the next item reuses the LDS
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+int size_class(int64_t s)
+{
+    return s <= 256 ? 0 : (s <= 1024 ? 1 : 2);
+}
+
+int64_t problem_size(const ne_problem_t &p)
+{
+    if (p.op == NE_OP_GEMM)
+        return std::max(p.n, std::max(p.K, p.N));
+    return p.N;
+}
+
+} // namespace
+
+struct BatchPlan {
+    void *table;
+    int64_t bytes;
+    int n_items;
+    int grid;
+};
+
+} // namespace ne
+
+using namespace ne;
+
+namespace {
+
+int params_for(int M, int r, ne_params_t *p)
+{
+    int rc = ne_params_default(M, 64, p);
+    if (rc)
+        return rc;
+    p->r_check = r;
+    return NE_OK;
+}
+
+int validate(const ne_problem_t &q, const ne_params_t &p)
+{
+    if (q.M < 3 || q.M > kMaxStreamsFused || q.r_check < 0 || q.r_check >= q.M)
+        return NE_EINVAL;
+    if (q.out_dtype != NE_I32 && q.out_dtype != NE_I64)
+        return NE_EINVAL;
+    if (!q.c || !q.d_hat)
+        return NE_EINVAL;
+    int64_t D = 0;
+    ne_range_bound(&p, &D);
+    if (q.op == NE_OP_GEMM) {
+        if (q.n <= 0 || q.N <= 0 || q.K <= 0 || q.K > kMaxK || !q.g)
+            return NE_EINVAL;
+        if (q.K % 16 || ((uintptr_t)q.c & 15) || ((uintptr_t)q.g & 15))
+            return NE_EALIGN;
+        if (q.K * 128 * 128 > D)
+            return NE_ERANGE;
+    } else if (q.op == NE_OP_CONV) {
+        if (q.N <= 0 || q.N > kMaxK || !q.g)
+            return NE_EINVAL;
+        if (q.N * 128 * 128 > D)
+            return NE_ERANGE;
+    } else if (q.op == NE_OP_PERM) {
+        if (q.N <= 0 || q.N > 0x7fffffff || !q.perm)
+            return NE_EINVAL;
+    } else {
+        return NE_EINVAL;
+    }
+    if ((uintptr_t)q.d_hat % q.out_dtype || (uintptr_t)q.flags % 4 || (uintptr_t)q.n_bad % 8)
+        return NE_EALIGN;
+    return NE_OK;
+}
+
+// Cost estimate (seconds on one CU) used only to order items longest-first.
+double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
+{
+    if (q.op == NE_OP_GEMM)
+        return 2.0 * 2.0 * q.M * 32.0 * bn * q.K / 8.0e12;
+    if (q.op == NE_OP_CONV)
+        return (double)q.M * kConvT * q.N / 2.0e10;
+    return (double)chunk * q.M * (1.0 + q.out_dtype) / 2.0e10;
+}
+
+struct Built {
+    std::vector<DevProblem> probs;
+    std::vector<DevItem> items;
+};
+
+int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuning, Built &out)
+{
+    struct Tmp {
+        DevItem it;
+        double cost;
+    };
+    std::vector<Tmp> tmp;
+    out.probs.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const ne_problem_t &q = problems[i];
+        ne_params_t p;
+        if (params_for(q.M, q.r_check, &p))
+            return NE_EINVAL;
+        int rc = validate(q, p);
+        if (rc)
+            return rc;
+        const int cls = size_class(problem_size(q));
+        DevProblem &d = out.probs[i];
+        memset(&d, 0, sizeof d);
+        d.op = q.op;
+        d.M = q.M;
+        d.l = p.l;
+        d.r = q.r_check;
+        d.out64 = q.out_dtype == NE_I64;
+        d.n = q.n;
+        d.K = q.K;
+        d.N = q.N;
+        d.c = q.c;
+        d.g = q.g;
+        d.perm = q.perm;
+        d.scale = q.scale;
+        d.add = q.add;
+        d.dhat = q.d_hat;
+        d.flags = q.flags;
+        d.n_bad = q.n_bad;
+        if (q.op == NE_OP_GEMM) {
+            int bn = tuning ? tuning->gemm_bn[q.M - 3][cls] : (q.M <= 4 && cls == 2 ? 256 : 128);
+            if (bn != 256 || q.M > 4)
+                bn = 128;
+            d.bn = bn;
+            d.tiles_m = (int)((q.n + 31) / 32);
+            d.tiles_n = (int)((q.N + bn - 1) / bn);
+            const double c1 = item_cost(q, bn, 0);
+            for (int tn = 0; tn < d.tiles_n; ++tn)
+                for (int tm = 0; tm < d.tiles_m; ++tm)
+                    tmp.push_back({{i, tm, tn, 0}, c1});
+        } else if (q.op == NE_OP_CONV) {
+            const int blocks = (int)((q.N + kConvT - 1) / kConvT);
+            const double c1 = item_cost(q, 0, 0);
+            for (int b = 0; b < blocks; ++b)
+                tmp.push_back({{i, b, 0, 0}, c1});
+        } else {
+            int64_t chunk = tuning ? tuning->perm_chunk[q.M - 3][cls] : 16384;
+            if (chunk < 64)
+                chunk = 64;
+            chunk = (chunk + 63) / 64 * 64;
+            d.chunk = chunk;
+            const int chunks = (int)((q.N + chunk - 1) / chunk);
+            const double c1 = item_cost(q, 0, chunk);
+            for (int b = 0; b < chunks; ++b)
+                tmp.push_back({{i, b, 0, 0}, c1});
+        }
+    }
+    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; });
+    out.items.resize(tmp.size());
+    for (size_t i = 0; i < tmp.size(); ++i)
+        out.items[i] = tmp[i].it;
+    return NE_OK;
+}
+
+int64_t table_bytes(const Built &b)
+{
+    return kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem) +
+           (int64_t)b.items.size() * sizeof(DevItem);
+}
+
+int upload(const Built &b, void *table_dev)
+{
+    std::vector<uint8_t> host(table_bytes(b), 0);
+    DevHeader h{};
+    h.counter = 0;
+    h.n_items = (int32_t)b.items.size();
+    h.n_problems = (int32_t)b.probs.size();
+    h.problems_off = kHeaderBytes;
+    h.items_off = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem);
+    memcpy(host.data(), &h, sizeof h);
+    if (!b.probs.empty())
+        memcpy(host.data() + h.problems_off, b.probs.data(), b.probs.size() * sizeof(DevProblem));
+    if (!b.items.empty())
+        memcpy(host.data() + h.items_off, b.items.data(), b.items.size() * sizeof(DevItem));
+    return hipMemcpy(table_dev, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess
+               ? NE_OK
+               : NE_ELAUNCH;
+}
+
+int cu_count()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
+int launch_plan(const BatchPlan &bp, hipStream_t s)
+{
+    if (bp.n_items == 0)
+        return NE_OK;
+    k_batch_reset<<<1, 1, 0, s>>>((DevHeader *)bp.table);
+    k_batch<<<bp.grid, kBatchThreads, 0, s>>>((const uint8_t *)bp.table);
+    return launch_status();
+}
+
+} // namespace
+
+extern "C" {
+
+int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tuning_t *tuning,
+                  void *table_dev, int64_t table_bytes_avail, int64_t *table_needed,
+                  ne_batch_t **plan)
+{
+    if (count < 0 || (count > 0 && !problems) || !table_needed)
+        return NE_EINVAL;
+    Built b;
+    int rc = build(problems, count, tuning, b);
+    if (rc)
+        return rc;
+    *table_needed = table_bytes(b);
+    if (!table_dev)
+        return NE_OK; // size query
+    if (!plan || table_bytes_avail < *table_needed || ((uintptr_t)table_dev & 255))
+        return table_bytes_avail < *table_needed ? NE_EINVAL : NE_EALIGN;
+    rc = upload(b, table_dev);
+    if (rc)
+        return rc;
+    auto *bp = (BatchPlan *)malloc(sizeof(BatchPlan));
+    if (!bp)
+        return NE_EINVAL;
+    bp->table = table_dev;
+    bp->bytes = *table_needed;
+    bp->n_items = (int)b.items.size();
+    bp->grid = std::min<int>(cu_count(), std::max(1, bp->n_items));
+    *plan = (ne_batch_t *)bp;
+    return NE_OK;
+}
+
+int ne_batch_run(const ne_batch_t *plan, ne_stream_t stream)
+{
+    if (!plan)
+        return NE_EINVAL;
+    return launch_plan(*(const BatchPlan *)plan, (hipStream_t)stream);
+}
+
+int ne_batch_items(const ne_batch_t *plan)
+{
+    return plan ? ((const BatchPlan *)plan)->n_items : -1;
+}
+
+void ne_batch_free(ne_batch_t *plan) { free(plan); }
+
+int ne_batch_autotune(const ne_problem_t *problems, int32_t count, void *table_dev,
+                      int64_t table_bytes_avail, int32_t reps, ne_batch_tuning_t *out,
+                      ne_stream_t stream)
+{
+    if (!out || count < 0 || (count > 0 && !problems) || !table_dev || reps < 1)
+        return NE_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    // defaults
+    for (int m = 0; m < 6; ++m)
+        for (int c = 0; c < 3; ++c) {
+            out->gemm_bn[m][c] = (m <= 1 && c == 2) ? 256 : 128;
+            out->perm_chunk[m][c] = 16384;
+        }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return NE_ELAUNCH;
+    int rc = NE_OK;
+    for (int op = NE_OP_GEMM; op <= NE_OP_PERM && rc == NE_OK; ++op) {
+        if (op == NE_OP_CONV)
+            continue; // one block shape only
+        for (int m = 3; m <= kMaxStreamsFused && rc == NE_OK; ++m)
+            for (int cls = 0; cls < 3 && rc == NE_OK; ++cls) {
+                std::vector<ne_problem_t> sub;
+                for (int i = 0; i < count; ++i)
+                    if (problems[i].op == op && problems[i].M == m &&
+                        size_class(problem_size(problems[i])) == cls)
+                        sub.push_back(problems[i]);
+                if (sub.empty())
+                    continue;
+                std::vector<int64_t> cands;
+                if (op == NE_OP_GEMM) {
+                    cands.push_back(128);
+                    if (m <= 4)
+                        cands.push_back(256);
+                } else {
+                    cands = {4096, 16384, 65536};
+                }
+                double best = 1e30;
+                for (int64_t cand : cands) {
+                    ne_batch_tuning_t t = *out;
+                    if (op == NE_OP_GEMM)
+                        t.gemm_bn[m - 3][cls] = (int32_t)cand;
+                    else
+                        t.perm_chunk[m - 3][cls] = cand;
+                    int64_t need = 0;
+                    ne_batch_t *bp = nullptr;
+                    rc = ne_batch_plan(sub.data(), (int)sub.size(), &t, table_dev,
+                                       table_bytes_avail, &need, &bp);
+                    if (rc)
+                        break;
+                    rc = ne_batch_run(bp, s); // warm-up
+                    (void)hipEventRecord(e0, s);
+                    for (int r = 0; r < reps && rc == NE_OK; ++r)
+                        rc = ne_batch_run(bp, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ne_batch_free(bp);
+                    if (rc == NE_OK && ms < best) {
+                        best = ms;
+                        if (op == NE_OP_GEMM)
+                            out->gemm_bn[m - 3][cls] = (int32_t)cand;
+                        else
+                            out->perm_chunk[m - 3][cls] = cand;
+                    }
+                }
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+} // extern "C"

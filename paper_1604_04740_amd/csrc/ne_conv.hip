@@ -1,13 +1,16 @@
-// ne_conv.hip -- circular convolution of every entangled stream with the
-// shared kernel g (section II, the star operator), on 64-bit words:
+// ne_conv.hip -- circular convolution of entangled streams with a shared
+// kernel g (section II, the star operator), on 64-bit words:
 //     delta[m][t] = sum_j eps[m][(t - j) mod N] * g[j]   (mod 2^64).
 //
-// Direct evaluation: a workgroup owns 256 consecutive outputs of one stream
-// and walks the kernel in 256-tap tiles; each tile stages the 256 taps and
-// the 511 input words they touch in LDS, so every global word is read once
-// per tile and every thread does 256 multiply-adds from LDS.
-#include "ne_arith.h"
-#include "ne_internal.h"
+// Direct evaluation on the vector ALUs.  A workgroup owns 256 consecutive
+// output positions and walks the kernel in 256-tap tiles; each tile stages
+// the 256 taps and the 511 input words they touch in LDS, so every global
+// word is read once per tile and each thread does 256 multiply-adds per
+// stream from LDS.
+//
+//   k_circconv_direct   staged: one stream per workgroup row, eps given
+//   k_circconv_fused<M> fused (device code in ne_conv_impl.h)
+#include "ne_conv_impl.h"
 
 namespace ne {
 namespace {
@@ -48,6 +51,24 @@ __global__ __launch_bounds__(kT) void k_circconv_direct(const int64_t *__restric
         delta[m * N + t0 + tid] = (int64_t)acc;
 }
 
+template <int M>
+int launch_fused_m(const void *c, int c_dtype, const int8_t *g, void *dhat, int out64,
+                   uint32_t *flags, unsigned long long *n_bad, int64_t N, int l, int r,
+                   hipStream_t s)
+{
+    const dim3 grid((unsigned)((N + kT - 1) / kT));
+    if (c_dtype == NE_I8)
+        k_circconv_fused<M, int8_t><<<grid, kT, 0, s>>>((const int8_t *)c, g, dhat, out64, flags,
+                                                         n_bad, N, l, r);
+    else if (c_dtype == NE_I32)
+        k_circconv_fused<M, int32_t><<<grid, kT, 0, s>>>((const int32_t *)c, g, dhat, out64,
+                                                          flags, n_bad, N, l, r);
+    else
+        k_circconv_fused<M, int64_t><<<grid, kT, 0, s>>>((const int64_t *)c, g, dhat, out64,
+                                                          flags, n_bad, N, l, r);
+    return launch_status();
+}
+
 } // namespace
 
 int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
@@ -57,6 +78,21 @@ int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t
     const dim3 grid((unsigned)((N + kT - 1) / kT), (unsigned)M);
     k_circconv_direct<<<grid, kT, 0, s>>>(eps, g, delta, N);
     return launch_status();
+}
+
+int launch_circconv_fused(const void *c, int c_dtype, const int8_t *g, void *dhat, int out64,
+                          uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                          int r, hipStream_t s)
+{
+    switch (M) {
+    case 3: return launch_fused_m<3>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    case 4: return launch_fused_m<4>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    case 5: return launch_fused_m<5>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    case 6: return launch_fused_m<6>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    case 7: return launch_fused_m<7>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    case 8: return launch_fused_m<8>(c, c_dtype, g, dhat, out64, flags, n_bad, N, l, r, s);
+    default: return NE_EUNSUP;
+    }
 }
 
 } // namespace ne

@@ -5,6 +5,7 @@
 // are coalesced across the wavefront.
 #include "ne_arith.h"
 #include "ne_internal.h"
+#include "ne_perm_impl.h"
 
 namespace ne {
 namespace {
@@ -178,7 +179,35 @@ template <int M> struct PermL {
     }
 };
 
+template <int M> struct PermFusedL {
+    static int run(const void *c, int dt, const int32_t *perm, const int64_t *scale,
+                   const int64_t *add, void *dhat, int out64, uint32_t *flags,
+                   unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
+    {
+        const unsigned g = grid_for(N, kThreads);
+        if (dt == NE_I8)
+            k_permute_scale_fused<M, int8_t><<<g, kThreads, 0, s>>>(
+                (const int8_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
+        else if (dt == NE_I32)
+            k_permute_scale_fused<M, int32_t><<<g, kThreads, 0, s>>>(
+                (const int32_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
+        else
+            k_permute_scale_fused<M, int64_t><<<g, kThreads, 0, s>>>(
+                (const int64_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
+        return launch_status();
+    }
+};
+
 } // namespace
+
+int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
+                               const int64_t *scale, const int64_t *add, void *dhat, int out64,
+                               uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                               int r, hipStream_t s)
+{
+    return dispatch_m<PermFusedL>(M, c, c_dtype, perm, scale, add, dhat, out64, flags, n_bad, N,
+                                  l, r, s);
+}
 
 int launch_entangle(const void *c, int c_dtype, int64_t *eps, int64_t N, int M, int l,
                     hipStream_t s)

@@ -33,6 +33,11 @@ int launch_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t 
                          const int64_t *add, int64_t *delta, int64_t N, int M, int l,
                          hipStream_t s);
 
+int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
+                               const int64_t *scale, const int64_t *add, void *dhat, int out64,
+                               uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                               int r, hipStream_t s);
+
 // ---- matrix-core GEMMs (ne_gemm.hip) ----
 int launch_gemm_plain(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,
                       int64_t N, hipStream_t s);
@@ -48,6 +53,9 @@ int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *fl
 // ---- circular convolution (ne_conv.hip) ----
 int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
                         int64_t N, int M, hipStream_t s);
+int launch_circconv_fused(const void *c, int c_dtype, const int8_t *g, void *dhat, int out64,
+                          uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                          int r, hipStream_t s);
 
 // Grid size for grid-stride element-wise kernels.
 inline unsigned grid_for(int64_t work, int threads)
