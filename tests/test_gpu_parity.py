@@ -110,7 +110,7 @@ def test_recover_every_lost_stream(ne, orc, M):
     p = ne.ne_params_default(M)
     N = 5000
     D = orc.range_bound(M, p.l, p.k)
-    lim = min(D, 1 << 31)
+    lim = min(D, (1 << 31) - 1)
     c = ne_synth.uniform_int(400 + M, 1, (M, N), -lim, lim + 1)
     delta = orc.entangle(c, 64, p.l)
     dd = [_t(delta[m]) for m in range(M)]
