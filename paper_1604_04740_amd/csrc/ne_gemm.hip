@@ -45,12 +45,13 @@ int launch_eps_l(const int64_t *eps, const int8_t *Bt, int64_t *delta, int64_t R
     return launch<EpsV<L>>(a, R, (K % 16 == 0) && aligned16(Bt), s);
 }
 
-template <int M>
-int launch_fused_m(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uint32_t *flags,
+template <int M, bool INJ>
+int launch_fused_v(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uint32_t *flags,
                    unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int l, int r,
                    const ne_inject_t *inj, hipStream_t s)
 {
-    typename FusedV<M>::Args a{};
+    using V = FusedV<M, FusedV<M>::BN, INJ>; // same tile as the default variant
+    typename V::Args a{};
     a.Bt = Bt;
     a.K = K;
     a.N = N;
@@ -62,13 +63,23 @@ int launch_fused_m(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uin
     a.l = l;
     a.r = r;
     a.out64 = out64;
-    if (inj && inj->count > 0) {
+    if (INJ) {
         a.inj_pos = inj->position;
         a.inj_stream = inj->stream;
         a.inj_mask = inj->xor_mask;
         a.inj_count = inj->count;
     }
-    return launch<FusedV<M>>(a, n, (K % 16 == 0) && aligned16(c) && aligned16(Bt), s);
+    return launch<V>(a, n, (K % 16 == 0) && aligned16(c) && aligned16(Bt), s);
+}
+
+template <int M>
+int launch_fused_m(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uint32_t *flags,
+                   unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int l, int r,
+                   const ne_inject_t *inj, hipStream_t s)
+{
+    if (inj && inj->count > 0)
+        return launch_fused_v<M, true>(c, Bt, dhat, out64, flags, n_bad, n, K, N, l, r, inj, s);
+    return launch_fused_v<M, false>(c, Bt, dhat, out64, flags, n_bad, n, K, N, l, r, inj, s);
 }
 
 template <int M>

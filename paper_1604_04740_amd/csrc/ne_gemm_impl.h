@@ -263,7 +263,7 @@ __device__ __forceinline__ void wait_vm_barrier()
 // `stage`: regions g = wave, wave + 4, ... of 1 KB; A regions first (source
 // by source), then B.
 template <int NSRC, int BMS, int BN, int BK_, int PART = 0, int NPARTS = 1>
-__device__ __forceinline__ void dma_tile(int8_t *stage, const rsrc_t (&ra)[NSRC], rsrc_t rb,
+__device__ __forceinline__ void dma_tile(int8_t *stage, const rsrc_t *ra, rsrc_t rb,
                                          int64_t k0, int64_t K, int wave, int lane)
 {
     constexpr int C = BK_ / 16, RPR = 1024 / BK_, RPS = BMS / RPR; // regions per source
@@ -348,7 +348,7 @@ __device__ __forceinline__ void interleave()
 
 // k-step ks issues part ks of the next tile's DMA (KS parts in total).
 template <int NSRC, int BMS, int BN, int BK_, int KS>
-__device__ __forceinline__ void dma_part(int ks, int8_t *stage, const rsrc_t (&ra)[NSRC],
+__device__ __forceinline__ void dma_part(int ks, int8_t *stage, const rsrc_t *ra,
                                          rsrc_t rb, int64_t k0, int64_t K, int wave, int lane)
 {
     if (ks == 0) dma_tile<NSRC, BMS, BN, BK_, 0, KS>(stage, ra, rb, k0, K, wave, lane);
@@ -443,10 +443,10 @@ __device__ __forceinline__ void gemm_tile_dma(const typename V::Args &args, int 
         v4i fa[2][NSRC][RB], fb[2][CB];
         load_frags<NSRC, RB, CB, BMS, BK_, A_BYTES>(cur, 0, wm, wn, lane, fa[0], fb[0]);
 #pragma unroll
-        for (int ks = 0; ks < BK_ / 32; ++ks) {
+        for (int ks = 0; ks < KS; ++ks) {
             __builtin_amdgcn_sched_barrier(0); // each k-step is its own scheduling region
             const int c = ks & 1;
-            if (ks + 1 < BK_ / 32)
+            if (ks + 1 < KS)
                 load_frags<NSRC, RB, CB, BMS, BK_, A_BYTES>(cur, ks + 1, wm, wn, lane, fa[c ^ 1],
                                                             fb[c ^ 1]);
             // this k-step's share of the next tile's global -> LDS copies
@@ -458,12 +458,15 @@ __device__ __forceinline__ void gemm_tile_dma(const typename V::Args &args, int 
 #pragma unroll
                     for (int j = 0; j < CB; ++j)
                         acc[p][i][j] = mfma(fa[c][V::src(p)][i], fb[c][j], acc[p][i][j]);
-            if (ks + 1 < BK_ / 32)
+            if (ks + 1 < KS)
                 interleave<P * RB * CB, NSRC * RB + CB, DMA_PER_KS>();
             else
                 interleave<P * RB * CB, 0, DMA_PER_KS>();
         }
     }
+    // The dummy loads of the last iterations still target the LDS ring: let
+    // them land before the caller (the batch kernel) reuses that memory.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
 
     V::epilogue(args, acc, row0, col0, wm, wn, lane);
 }
@@ -639,7 +642,10 @@ struct EpsV {
 // Workgroup tile: 32 rows of every stream x BN columns; each wavefront owns
 // BN/4 columns of those rows for all M streams and both digits, i.e.
 // 2 * M * (BN / 128) accumulator blocks (at most 256 registers).
-template <int M, int BN_ = (M <= 4) ? 256 : 128>
+// INJ: the variant that XORs a device list of faults into the entangled
+// words before the check (fault-injection runs); a separate kernel, so the
+// production kernel carries none of it.
+template <int M, int BN_ = (M <= 4) ? 256 : 128, bool INJ = false>
 struct FusedV {
     static constexpr int NSRC = M, P = 2 * M, BMS = 32, BN = BN_, WM = 1, WN = 4;
     static constexpr int kOcc = 1;
@@ -719,9 +725,16 @@ struct FusedV {
                 const bool valid = row < g.n && col < g.N;
                 int64_t d[M], o[M];
 #pragma unroll
-                for (int s = 0; s < M; ++s)
-                    d[s] = (int64_t)((uint64_t)(int64_t)acc[s][0][j][r] +
-                                     ((uint64_t)(int64_t)acc[M + s][0][j][r] << g.l));
+                for (int s = 0; s < M; ++s) {
+                    // Copy the two accumulators out of the AGPRs here, at their
+                    // use: left to itself the compiler moves all of them out
+                    // right after the main loop and spills.
+                    int lo, hi;
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(acc[s][0][j][r]));
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(acc[M + s][0][j][r]));
+                    d[s] = (int64_t)((uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << g.l));
+                }
+                if constexpr (INJ)
                 for (int64_t f = f_beg; f < f_end; ++f) {
                     if (g.inj_pos[f] == row * g.N + col) {
                         const int st = (g.inj_stream[f] - g.r + M) % M; // its slot
@@ -766,7 +779,7 @@ struct FusedV {
         // Injected faults of this tile: positions are sorted, so the tile's
         // rows form one contiguous range of the list.
         int64_t fb = 0, fe = 0;
-        if (g.inj_count > 0) {
+        if (INJ && g.inj_count > 0) {
             const int64_t rows_end = row0 + BMS < g.n ? row0 + BMS : g.n;
             const int64_t lo_key = row0 * g.N, hi_key = rows_end * g.N;
             int64_t lo = 0, hi = g.inj_count;
