@@ -128,8 +128,10 @@ int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t 
  *   eps       device, [M][N] int64;  eps_bits as for ne_lsb_gemm.
  *   g         device, [N] int8.
  *   delta     device, [M][N] int64; must not overlap eps.
- *   N         1 .. 131071.  Evaluated directly with 64-bit multiply-adds
- *             (the operation is latency-bound at these lengths).
+ *   N         1 .. 131071.  Evaluated on int8 matrix cores: each block of
+ *             1024 outputs is a Toeplitz x Hankel matrix product over the
+ *             taps, the words split into min(8, eps_bits/8 + 1) signed int8
+ *             digits with exact int32 accumulation, recombined mod 2^64.
  */
 int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
                     int64_t N, const ne_params_t *p, ne_stream_t stream);
@@ -242,9 +244,15 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
                     ne_stream_t stream);
 
 /*
- * Fused circular convolution, one launch: entangle in the staging of each
- * kernel tile, the star operator of section II on the entangled words, then
- * disentangle and check (section III-C).  delta never reaches memory.
+ * Fused circular convolution, one launch: the star operator of section II on
+ * the entangled words, then disentangle and check (section III-C).  delta
+ * never reaches memory.  Each block of 1024 outputs is a Toeplitz x Hankel
+ * product on int8 matrix cores; the entangled word of stream m is formed in
+ * the accumulation, conv(c_m, g) + 2^l conv(c_{m-1}, g), with the two
+ * products of every stream computed separately (a fault in one stream's
+ * computation reaches only that stream).  Inputs wider than a byte are
+ * split into signed int8 digits (1 digit if c_bits <= 8, else
+ * min(8, c_bits/8 + 1)), one pass over the taps per digit.
  *   c         device, [M][N] of c_dtype (NE_I8, NE_I32 or NE_I64).
  *   c_bits    bound on the inputs: |c| < 2^(c_bits-1); with |g| <= 128 it
  *             gives the a-priori bound N * 2^(c_bits-1) * 128, which must not

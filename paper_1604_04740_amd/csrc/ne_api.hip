@@ -335,8 +335,8 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
     if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 ||
         (uintptr_t)n_bad % 8)
         return NE_EALIGN;
-    return launch_circconv_fused(c, c_dtype, g, d_hat, out_dtype == NE_I64, flags, n_bad, N, p->M,
-                                 p->l, p->r_check, hs(stream));
+    return launch_circconv_fused(c, c_dtype, c_bits, g, d_hat, out_dtype == NE_I64, flags, n_bad,
+                                 N, p->M, p->l, p->r_check, hs(stream));
 }
 
 int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,

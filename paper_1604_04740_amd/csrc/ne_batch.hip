@@ -2,7 +2,7 @@
 // operation) in one persistent launch.
 //
 // Host side (setup, not graph-capturable): ne_batch_plan turns a problem
-// list into work items -- one per GEMM output tile, one per 256-position
+// list into work items -- one per GEMM output tile, one per 1024-position
 // convolution block, one per permute/scale chunk -- orders them
 // longest-first by a cost estimate (so the long items start early and the
 // short ones fill the tail), and writes the problem table and item list
@@ -102,10 +102,20 @@ __device__ __forceinline__ void run_gemm(const DevProblem &P, int tm, int tn, in
 template <int M>
 __device__ __forceinline__ void run_conv_m(const DevProblem &P, int block, int8_t *lds)
 {
-    auto *xs = (int64_t(*)[2 * kConvT])lds;
-    auto *gs = (int32_t *)(lds + (size_t)M * 2 * kConvT * sizeof(int64_t));
-    conv_fused_block<M, int8_t>((const int8_t *)P.c, (const int8_t *)P.g, P.dhat, P.out64,
-                                P.flags, P.n_bad, P.N, P.l, P.r, (int64_t)block * kConvT, xs, gs);
+    ConvJob J{};
+    J.x = P.c;
+    J.x_dtype = NE_I8;
+    J.digits = 1;
+    J.g = (const int8_t *)P.g;
+    J.out = P.dhat;
+    J.out64 = P.out64;
+    J.flags = P.flags;
+    J.n_bad = P.n_bad;
+    J.N = P.N;
+    J.M = M;
+    J.l = P.l;
+    J.r = P.r;
+    conv_block<M, true>(J, block, lds);
 }
 
 __device__ __forceinline__ void run_conv(const DevProblem &P, int block, int8_t *lds)
@@ -146,6 +156,7 @@ __device__ __forceinline__ void run_perm(const DevProblem &P, int chunk)
 constexpr int kBatchLds = 3 * 49152; // largest GEMM ring (M = 4, BN = 256 / M = 8, BN = 128)
 static_assert(dma_lds_bytes<FusedV<4, 256>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
 static_assert(dma_lds_bytes<FusedV<8, 128>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
+static_assert(cv_lds_bytes(kCvMaxSlots) <= kBatchLds, "LDS");
 
 __global__ void k_batch_reset(DevHeader *h) { h->counter = 0u; }
 
@@ -254,7 +265,7 @@ double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
     if (q.op == NE_OP_GEMM)
         return 2.0 * 2.0 * q.M * 32.0 * bn * q.K / 8.0e12;
     if (q.op == NE_OP_CONV)
-        return (double)q.M * kConvT * q.N / 2.0e10;
+        return 3.0 * q.M * kCvBlock * q.N / 4.0e12; // matrix-core MACs + staging
     return (double)chunk * q.M * (1.0 + q.out_dtype) / 2.0e10;
 }
 
@@ -310,7 +321,7 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
                 for (int tm = 0; tm < d.tiles_m; ++tm)
                     tmp.push_back({{i, tm, tn, 0}, c1});
         } else if (q.op == NE_OP_CONV) {
-            const int blocks = (int)((q.N + kConvT - 1) / kConvT);
+            const int blocks = (int)((q.N + kCvBlock - 1) / kCvBlock);
             const double c1 = item_cost(q, 0, 0);
             for (int b = 0; b < blocks; ++b)
                 tmp.push_back({{i, b, 0, 0}, c1});

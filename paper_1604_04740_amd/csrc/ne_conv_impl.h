@@ -1,12 +1,43 @@
-// ne_conv_impl.h -- fused circular convolution device code (shared by the
-// convolution entry point and the batched persistent kernel).
+// ne_conv_impl.h -- circular convolution on the int8 matrix cores (device
+// code shared by the convolution entry points and the batched kernel).
 //
-// Fused: c [M][N] (int8/int32/int64) -> d_hat [M][N] (int32/int64) + flags.
-// All M streams of a position are handled by one thread: the staging of
-// each 256-tap tile entangles c into eps (section III-C) in LDS, the taps
-// are applied with 64-bit multiply-adds, and the epilogue disentangles and
-// checks (delta never reaches memory).  Each wavefront covers 64
-// consecutive positions, i.e. whole flag words.
+// The star operator of section II, y[t] = sum_j x[(t - j) mod N] g[j], for
+// the 1024 outputs t = t0 + 32 a + p (a, p in 0..31) of one block is a
+// 32 x 32 matrix product over the tap index i in [0, N):
+//     Y[a][p] = sum_i A[a][i] B[i][p],
+//     A[a][i] = x[(t0 + 32 a - i) mod N]     (Toeplitz in a, i)
+//     B[i][p] = g[(p + i) mod N]             (Hankel in i, p; 0 for i >= N)
+// (substitute j = (p + i) mod N).  Both operands are built in LDS from x
+// and g, one 32-tap k-step at a time feeds v_mfma_i32_32x32x32_i8.
+//
+// Words wider than a byte are split into signed int8 digits (balanced, base
+// 256): x = sum_d 256^d x_d.  Each digit is its own pass over the taps; the
+// int32 accumulators are exact (|sum| <= N * 128 * 128 < 2^31 for
+// N <= 131071) and are folded into 64-bit words (mod 2^64) after the pass.
+//
+// Fused (section III-C): the sources are the plain streams c; slot s holds
+// stream (r + s) mod M, and the entangled output of slot s is
+//     delta_s = conv(c_s, g) + 2^l conv(c_{s-1}, g),
+// two independent accumulator sets per slot, so that a fault in one
+// stream's computation reaches only that stream's delta.  The epilogue
+// disentangles and checks (delta never reaches memory).
+// Staged: the sources are given 64-bit words (entangled streams) and delta
+// is written out.
+//
+// LDS, per workgroup (4 wavefronts):
+//   A rings   one 2048-byte ring per slot: byte v holds digit d of
+//             x[(t0 - v) mod N], so the 16 bytes a lane needs for row a at
+//             taps i0 + 16h .. +15 start at v = i0 + 16h - 32a (aligned).
+//             Chunks are XOR-swizzled (bit 0 ^= bit 4) so that the 16 rows
+//             a lane group reads hit 16 different bank groups.
+//   g copies  32 rings of 512 bytes (stride 528 for the banks): copy p
+//             holds B[i][p] at byte i mod 512, so column p's 16 taps are
+//             one aligned read.
+//   red       [slots][1024] uint64: the folded delta of the block.
+// Each 256-tap step is staged while the previous one is multiplied (the
+// rings slide: 256 new bytes per ring per step); one barrier per step.  The
+// four wavefronts take two k-steps of each 256-tap step and add their
+// folded partial sums into red with LDS atomics.
 #pragma once
 
 #include "ne_arith.h"
@@ -15,96 +46,296 @@
 namespace ne {
 namespace {
 
-constexpr int kConvT = 256;
+typedef int cv4i __attribute__((ext_vector_type(4)));
+typedef int cv16i __attribute__((ext_vector_type(16)));
 
-// Positions [t0, t0 + 256) of every stream; xs is M * 512 int64 and gs 256
-// int32 of LDS.  Called by k_circconv_fused and by the batched kernel.
-template <int M, typename T>
-__device__ __forceinline__ void conv_fused_block(const T *__restrict__ c,
-                                                 const int8_t *__restrict__ g,
-                                                 void *__restrict__ dhat, int out64,
-                                                 uint32_t *__restrict__ flags,
-                                                 unsigned long long *__restrict__ n_bad,
-                                                 int64_t N, int l, int r, int64_t t0,
-                                                 int64_t (*xs)[2 * kConvT], int32_t *gs)
+constexpr int kCvThreads = 256;
+constexpr int kCvBlock = 1024;    // outputs per block
+constexpr int kCvStep = 256;      // taps staged per step
+constexpr int kCvRing = 2048;     // bytes per A ring (>= 992 + 2 * 256)
+constexpr int kCvGRing = 512;     // bytes per g copy (>= 2 * 256)
+constexpr int kCvGStride = 528;   // bytes between g copies
+constexpr int kCvMaxSlots = 8;
+
+__host__ __device__ constexpr int cv_lds_bytes(int slots)
 {
-    constexpr int kT = kConvT;
-    const int tid = threadIdx.x, lane = tid & 63;
-    uint64_t acc[M];
-#pragma unroll
-    for (int s = 0; s < M; ++s)
-        acc[s] = 0;
-    for (int64_t j0 = 0; j0 < N; j0 += kT) {
-        gs[tid] = (j0 + tid < N) ? (int32_t)g[j0 + tid] : 0;
-        const int64_t base = t0 - j0 - (kT - 1);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int i = tid + h * kT;
-            if (i < 2 * kT - 1) {
-                int64_t idx = (base + i) % N;
-                if (idx < 0)
-                    idx += N;
-                // slot s holds stream (r + s) mod M: load and entangle in slot order
-                int64_t v[M];
-#pragma unroll
-                for (int s = 0; s < M; ++s)
-                    v[s] = (int64_t)c[(int64_t)((r + s) % M) * N + idx];
-#pragma unroll
-                for (int s = 0; s < M; ++s)
-                    xs[s][i] = entangle_word(v[s], v[(s + M - 1) % M], l);
-            }
-        }
-        __syncthreads();
-        const int taps = (N - j0 < kT) ? (int)(N - j0) : kT;
-        for (int jj = 0; jj < taps; ++jj) {
-            const uint64_t gv = (uint64_t)(int64_t)gs[jj];
-#pragma unroll
-            for (int s = 0; s < M; ++s)
-                acc[s] += (uint64_t)xs[s][tid - jj + kT - 1] * gv;
-        }
-        __syncthreads();
-    }
-    const int64_t n = t0 + tid;
-    const bool valid = n < N;
-    int64_t d[M], o[M];
-#pragma unroll
-    for (int s = 0; s < M; ++s)
-        d[s] = (int64_t)acc[s];
-    const bool f = disentangle_rot<M>(d, l, o) && valid;
-    if (valid) {
-#pragma unroll
-        for (int s = 0; s < M; ++s) {
-            const int64_t idx = (int64_t)((r + s) % M) * N + n;
-            if (out64)
-                ((int64_t *)dhat)[idx] = o[s];
-            else
-                ((int32_t *)dhat)[idx] = (int32_t)o[s];
-        }
-    }
-    const uint64_t mask = __ballot(f);
-    const int64_t words = (N + 31) / 32, w0 = (t0 + (tid & ~63)) / 32;
-    if (flags) {
-        if (lane == 0 && w0 < words)
-            flags[w0] = (uint32_t)mask;
-        if (lane == 32 && w0 + 1 < words)
-            flags[w0 + 1] = (uint32_t)(mask >> 32);
-    }
-    if (n_bad && lane == 0 && mask)
-        atomicAdd(n_bad, (unsigned long long)__popcll(mask));
+    return slots * kCvRing + 32 * kCvGStride + slots * kCvBlock * 8;
 }
 
-template <int M, typename T>
-__global__ __launch_bounds__(kConvT) void k_circconv_fused(const T *__restrict__ c,
-                                                           const int8_t *__restrict__ g,
-                                                           void *__restrict__ dhat, int out64,
-                                                           uint32_t *__restrict__ flags,
-                                                           unsigned long long *__restrict__ n_bad,
-                                                           int64_t N, int l, int r)
+// Number of balanced int8 digits for values with |x| < 2^(bits-1).
+__host__ __device__ inline int cv_digits(int bits)
 {
-    __shared__ int64_t xs[M][2 * kConvT];
-    __shared__ int32_t gs[kConvT];
-    conv_fused_block<M, T>(c, g, dhat, out64, flags, n_bad, N, l, r,
-                           (int64_t)blockIdx.x * kConvT, xs, gs);
+    return bits <= 8 ? 1 : (bits / 8 + 1 > 8 ? 8 : bits / 8 + 1);
+}
+
+struct ConvJob {
+    const void *x;              // fused: c [M][N]; staged: eps [M][N] int64
+    int x_dtype;                // NE_I8 / NE_I32 / NE_I64
+    int digits;                 // balanced int8 digits per value
+    const int8_t *g;            // [N]
+    void *out;                  // fused: d_hat (int32 or int64); staged: delta int64
+    int out64;
+    uint32_t *flags;            // fused: [ceil(N/32)] or NULL
+    unsigned long long *n_bad;  // fused: counter or NULL
+    int64_t N;
+    int M, l, r;
+    int s0;                     // staged: first stream of this workgroup
+};
+
+__device__ __forceinline__ int64_t cv_load(const void *x, int dt, int64_t i)
+{
+    if (dt == NE_I8)
+        return ((const int8_t *)x)[i];
+    if (dt == NE_I32)
+        return ((const int32_t *)x)[i];
+    return ((const int64_t *)x)[i];
+}
+
+__device__ __forceinline__ int8_t cv_digit(int64_t v, int d)
+{
+    int8_t e = digit(v);
+    for (int j = 0; j < d; ++j)
+        e = digit(v);
+    return e;
+}
+
+// Byte offset of ring coordinate v (any integer) inside an A ring.
+__device__ __forceinline__ int cv_ring_off(int64_t v)
+{
+    const int c = (int)((v & (kCvRing - 1)) >> 4);
+    return ((c ^ ((c >> 4) & 1)) << 4) | (int)(v & 15);
+}
+
+__device__ __forceinline__ int64_t cv_mod(int64_t a, int64_t N)
+{
+    int64_t m = a % N;
+    return m < 0 ? m + N : m;
+}
+
+// One thread's share of an A-ring step: ring coordinate v of every slot.
+template <int G>
+struct CvA {
+    int64_t val[G];
+    int64_t v;
+    __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int64_t t0,
+                                         int64_t v_)
+    {
+        v = v_;
+        const int64_t idx = cv_mod(t0 - v, J.N);
+#pragma unroll
+        for (int s = 0; s < G; ++s)
+            val[s] = stream[s] >= 0 ? cv_load(J.x, J.x_dtype, (int64_t)stream[s] * J.N + idx) : 0;
+    }
+    __device__ __forceinline__ void store(int8_t *rings, int d) const
+    {
+        const int off = cv_ring_off(v);
+#pragma unroll
+        for (int s = 0; s < G; ++s)
+            rings[s * kCvRing + off] = cv_digit(val[s], d);
+    }
+};
+
+// One thread's share of a g-copy step: 32 taps [i0, i0 + 32) of copy p.
+struct CvG {
+    uint32_t w[8];
+    int p;
+    int64_t i0;
+    __device__ __forceinline__ void load(const ConvJob &J, int64_t I, int tid)
+    {
+        p = tid >> 3;
+        i0 = I + 32 * (tid & 7);
+        const int64_t N = J.N, s = i0 + p;
+        if (i0 + 32 <= N && s + 36 <= N) {
+            // g[s .. s+31] from nine aligned dwords inside g
+            const uintptr_t a = (uintptr_t)(J.g + s);
+            const uint32_t *q = (const uint32_t *)(a & ~(uintptr_t)3);
+            const uint32_t sh = (uint32_t)(a & 3);
+            uint32_t u[9];
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                u[k] = q[k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], sh);
+        } else {
+            // wrap-around or past the last tap: byte by byte
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                uint32_t x = 0;
+                for (int b = 0; b < 4; ++b) {
+                    const int64_t i = i0 + 4 * k + b;
+                    const uint32_t byte =
+                        i < N ? (uint32_t)(uint8_t)J.g[cv_mod(i + p, N)] : 0u;
+                    x |= byte << (8 * b);
+                }
+                w[k] = x;
+            }
+        }
+    }
+    __device__ __forceinline__ void store(int8_t *gc) const
+    {
+        int8_t *dst = gc + p * kCvGStride + (int)(i0 & (kCvGRing - 1));
+        *(cv4i *)dst = cv4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
+        *(cv4i *)(dst + 16) = cv4i{(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+    }
+};
+
+// One block of 1024 outputs of G slots.  FUSED: G == M, disentangle and
+// check in the epilogue.  lds: cv_lds_bytes(G) bytes, 16-byte aligned.
+template <int G, bool FUSED>
+__device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
+{
+    constexpr int CH = FUSED ? 2 * G : G; // accumulator sets
+    int8_t *rings = lds;
+    int8_t *gc = lds + G * kCvRing;
+    auto *red = (unsigned long long *)(gc + 32 * kCvGStride);
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t N = J.N, t0 = block * kCvBlock;
+    const int64_t Np = (N + 31) & ~(int64_t)31;
+    const int steps = (int)((Np + kCvStep - 1) / kCvStep);
+    int stream[G];
+#pragma unroll
+    for (int s = 0; s < G; ++s)
+        stream[s] = FUSED ? (J.r + s) % J.M : (J.s0 + s < J.M ? J.s0 + s : -1);
+
+    for (int i = tid; i < G * kCvBlock; i += kCvThreads)
+        red[i] = 0;
+
+    const int a = lane & 31, h = lane >> 5;
+    for (int d = 0; d < J.digits; ++d) {
+        cv16i acc[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                acc[q][e] = 0;
+
+        // prologue: ring bytes v in [-992, 256) and g taps [0, 256)
+        for (int k = tid; k < 992 + kCvStep; k += kCvThreads) {
+            CvA<G> st;
+            st.load(J, stream, t0, (int64_t)k - 992);
+            st.store(rings, d);
+        }
+        {
+            CvG sg;
+            sg.load(J, 0, tid);
+            sg.store(gc);
+        }
+        __syncthreads();
+
+        for (int j = 0; j < steps; ++j) {
+            const int64_t I = (int64_t)j * kCvStep;
+            const bool more = j + 1 < steps;
+            CvA<G> na;
+            CvG ng;
+            if (more) {
+                na.load(J, stream, t0, I + kCvStep + tid);
+                ng.load(J, I + kCvStep, tid);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int64_t i0 = I + 64 * wave + 32 * kk;
+                if (i0 < Np) {
+                    const cv4i B = *(const cv4i *)(gc + a * kCvGStride +
+                                                   (int)((i0 + 16 * h) & (kCvGRing - 1)));
+                    cv4i A[G];
+#pragma unroll
+                    for (int s = 0; s < G; ++s)
+                        A[s] = *(const cv4i *)(rings + s * kCvRing +
+                                               cv_ring_off(i0 + 16 * h - 32 * a));
+#pragma unroll
+                    for (int s = 0; s < G; ++s) {
+                        acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[s], 0, 0, 0);
+                        if constexpr (FUSED)
+                            acc[G + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                A[(s + G - 1) % G], B, acc[G + s], 0, 0, 0);
+                    }
+                }
+            }
+            if (more) {
+                na.store(rings, d);
+                ng.store(gc);
+            }
+            __syncthreads();
+        }
+
+        // fold this digit's products into red (mod 2^64)
+#pragma unroll
+        for (int s = 0; s < G; ++s)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = 8 * (e >> 2) + 4 * h + (e & 3);
+                int lo, hi = 0;
+                asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(acc[s][e]));
+                if constexpr (FUSED)
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(acc[G + s][e]));
+                uint64_t v = (uint64_t)(int64_t)lo;
+                if constexpr (FUSED)
+                    v += (uint64_t)(int64_t)hi << J.l;
+                atomicAdd(&red[s * kCvBlock + 32 * row + a], v << (8 * d));
+            }
+        __syncthreads();
+    }
+
+    // epilogue: four groups of 256 consecutive outputs
+#pragma unroll 1
+    for (int q = 0; q < kCvBlock / kCvThreads; ++q) {
+        const int pos = q * kCvThreads + tid;
+        const int64_t t = t0 + pos;
+        const bool valid = t < N;
+        if constexpr (FUSED) {
+            int64_t dd[G], o[G];
+#pragma unroll
+            for (int s = 0; s < G; ++s)
+                dd[s] = (int64_t)red[s * kCvBlock + pos];
+            const bool flag = disentangle_rot<G>(dd, J.l, o) && valid;
+            if (valid) {
+#pragma unroll
+                for (int s = 0; s < G; ++s) {
+                    const int64_t idx = (int64_t)stream[s] * N + t;
+                    if (J.out64)
+                        ((int64_t *)J.out)[idx] = o[s];
+                    else
+                        ((int32_t *)J.out)[idx] = (int32_t)o[s];
+                }
+            }
+            const uint64_t mask = __ballot(flag);
+            const int64_t words = (N + 31) / 32, w0 = (t0 + q * kCvThreads + 64 * wave) / 32;
+            if (J.flags) {
+                if (lane == 0 && w0 < words)
+                    J.flags[w0] = (uint32_t)mask;
+                if (lane == 32 && w0 + 1 < words)
+                    J.flags[w0 + 1] = (uint32_t)(mask >> 32);
+            }
+            if (J.n_bad && lane == 0 && mask)
+                atomicAdd(J.n_bad, (unsigned long long)__popcll(mask));
+        } else {
+            if (valid) {
+#pragma unroll
+                for (int s = 0; s < G; ++s)
+                    if (stream[s] >= 0)
+                        ((int64_t *)J.out)[(int64_t)stream[s] * N + t] =
+                            (int64_t)red[s * kCvBlock + pos];
+            }
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kCvThreads) void k_conv_fused(const ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(M)];
+    conv_block<M, true>(J, blockIdx.x, lds);
+}
+
+template <int G>
+__global__ __launch_bounds__(kCvThreads) void k_conv_staged(ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
+    J.s0 = (int)blockIdx.y * G;
+    conv_block<G, false>(J, blockIdx.x, lds);
 }
 
 } // namespace

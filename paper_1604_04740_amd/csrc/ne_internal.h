@@ -53,9 +53,9 @@ int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *fl
 // ---- circular convolution (ne_conv.hip) ----
 int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
                         int64_t N, int M, hipStream_t s);
-int launch_circconv_fused(const void *c, int c_dtype, const int8_t *g, void *dhat, int out64,
-                          uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
-                          int r, hipStream_t s);
+int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, void *dhat,
+                          int out64, uint32_t *flags, unsigned long long *n_bad, int64_t N, int M,
+                          int l, int r, hipStream_t s);
 
 // Grid size for grid-stride element-wise kernels.
 inline unsigned grid_for(int64_t work, int threads)

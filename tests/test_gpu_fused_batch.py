@@ -49,6 +49,21 @@ def test_circconv_fused(ne, orc, M, N):
     assert np.array_equal(_h(dh32), ref["dhat"].astype(np.int32))
 
 
+@pytest.mark.parametrize("M,N,cdt,bits", [(6, 2500, np.int8, 8), (3, 700, np.int32, 20),
+                                          (4, 1024, np.int64, 14)])
+def test_circconv_fused_digit_counts(ne, orc, M, N, cdt, bits):
+    """One, two and three int8 digits per input value; full and ragged blocks."""
+    lo = -(1 << (bits - 1))
+    c = ne_synth.uniform_int(1350 + M + N, 1, (M, N), lo, -lo)
+    g = ne_synth.uniform_int(1350 + M + N, 2, (N,), -128, 128).astype(np.int8)
+    p = ne.ne_params_default(M)
+    p.r_check = M - 1
+    ref = orc.conv_pipeline(c, g.astype(np.int64), r=M - 1)
+    dh, fl, nb = ne.ne_circconv_fused(_t(c.astype(cdt)), _t(g), p, c_bits=bits)
+    assert np.array_equal(_h(dh), ref["dhat"])
+    assert int(nb.item()) == 0 and not _bits(_h(fl), N).any()
+
+
 def test_circconv_fused_range_check(ne):
     p = ne.ne_params_default(8)  # l = 8, k = 8: D = 127 * 2^48
     c = torch.zeros((8, 16), dtype=torch.int64, device=DEV)

@@ -196,6 +196,19 @@ def test_circconv_on_entangled_words(ne, orc, N):
     assert np.array_equal(_h(dh), plain) and int(nb.item()) == 0
 
 
+@pytest.mark.parametrize("M,N,bits", [(3, 1100, 64), (11, 700, 40), (4, 33, 9)])
+def test_circconv_any_words(ne, orc, M, N, bits):
+    """Staged convolution of arbitrary words (every digit count, more streams
+    than one workgroup takes, ragged blocks) against the oracle, mod 2^64."""
+    p = ne.ne_params_default(M)
+    raw = ne_synth.raw_u64(ne_synth.stream_key(850 + M + N, 1), M * N).view(np.int64)
+    x = (raw >> np.int64(64 - bits)).reshape(M, N)  # uniform in [-2^(bits-1), 2^(bits-1))
+    g = ne_synth.uniform_int(850 + M + N, 3, (N,), -128, 128).astype(np.int8)
+    ref = np.stack([orc.circconv(x[m], g.astype(np.int64)) for m in range(M)])
+    got = ne.ne_lsb_circconv(_t(x), bits, _t(g), p)
+    assert np.array_equal(_h(got), ref)
+
+
 # ------------------------------------------------------------- fused GEMM
 
 FUSED = [(3, 64, 64, 64), (4, 100, 200, 300), (4, 33, 17, 45), (3, 65, 130, 257),
