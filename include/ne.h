@@ -132,9 +132,25 @@ int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t 
  *             1024 outputs is a Toeplitz x Hankel matrix product over the
  *             taps, the words split into min(8, eps_bits/8 + 1) signed int8
  *             digits with exact int32 accumulation, recombined mod 2^64.
+ *   workspace device scratch of ne_circconv_workspace(N, M, 0) bytes, or
+ *             NULL.  With it the taps of every block are split over
+ *             workgroups (64-bit partial sums in the workspace, then a
+ *             reduction launch), which fills the chip when N is small; with
+ *             NULL one workgroup computes each block.  Caller-owned, 8-byte
+ *             aligned, must not overlap the other arguments; its contents on
+ *             entry do not matter.  A workspace smaller than required is
+ *             NE_EINVAL.
  */
 int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
-                    int64_t N, const ne_params_t *p, ne_stream_t stream);
+                    int64_t N, const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                    ne_stream_t stream);
+
+/*
+ * Workspace bytes that ne_lsb_circconv (fused = 0) or ne_circconv_fused
+ * (fused = 1) uses for N taps and M streams; 0 when the taps are not split
+ * (then the workspace argument is ignored), and 0 for invalid sizes.
+ */
+int64_t ne_circconv_workspace(int64_t N, int32_t M, int32_t fused);
 
 /*
  * Fixed permutation, scaling and addition on the entangled streams (section
@@ -262,11 +278,12 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
  *   flags     device, [ceil(N/32)] uint32 bitmask, or NULL.
  *   n_bad     device counter (incremented), or NULL.
  *   N         1 .. 131071.
+ *   workspace as for ne_lsb_circconv, ne_circconv_workspace(N, M, 1) bytes.
  */
 int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g,
                       void *d_hat, int32_t out_dtype, uint32_t *flags,
                       unsigned long long *n_bad, int64_t N, const ne_params_t *p,
-                      ne_stream_t stream);
+                      void *workspace, int64_t workspace_bytes, ne_stream_t stream);
 
 /*
  * Fused permutation + scaling + addition, one launch (section II, op in

@@ -20,7 +20,7 @@ __all__ = [
     "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
-    "ne_circconv_fused", "ne_permute_scale_fused", "Inject", "Problem", "Batch", "ne_batch_plan",
+    "ne_circconv_fused", "ne_circconv_workspace", "ne_permute_scale_fused", "Inject", "Problem", "Batch", "ne_batch_plan",
     "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
 
@@ -84,7 +84,8 @@ def lib():
             "ne_range_bound": ([P, ctypes.POINTER(_i64)], ctypes.c_int),
             "ne_entangle": ([_vp, _i32, _vp, _i64, P, _vp], ctypes.c_int),
             "ne_lsb_gemm": ([_vp, _i32, _vp, _vp, _i64, _i64, _i64, P, _vp], ctypes.c_int),
-            "ne_lsb_circconv": ([_vp, _i32, _vp, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_lsb_circconv": ([_vp, _i32, _vp, _vp, _i64, P, _vp, _i64, _vp], ctypes.c_int),
+            "ne_circconv_workspace": ([_i64, _i32, _i32], _i64),
             "ne_lsb_permute_scale": ([_vp, _vp, _vp, _vp, _vp, _i64, P, _vp], ctypes.c_int),
             "ne_disentangle_check": ([_vp, _vp, _vp, _vp, _i64, P, _vp], ctypes.c_int),
             "ne_recover": ([ctypes.POINTER(_vp), _i32, _vp, _vp, _i64, P, _vp], ctypes.c_int),
@@ -93,8 +94,8 @@ def lib():
             "ne_plain_gemm_i8": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp], ctypes.c_int),
             "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp],
                                 ctypes.c_int),
-            "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp],
-                                  ctypes.c_int),
+            "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp,
+                                   _i64, _vp], ctypes.c_int),
             "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
                                         _vp], ctypes.c_int),
             "ne_batch_plan": ([ctypes.POINTER(_Problem), _i32, ctypes.POINTER(_Tuning), _vp, _i64,
@@ -194,16 +195,30 @@ def ne_lsb_gemm(eps: torch.Tensor, eps_bits: int, Gt: torch.Tensor, p: Params,
     return out
 
 
+def ne_circconv_workspace(N: int, M: int, fused: bool) -> int:
+    return int(lib().ne_circconv_workspace(N, M, 1 if fused else 0))
+
+
+def _conv_ws(workspace, N, M, fused, device):
+    """workspace=True: allocate what the library asks for; None/False: none."""
+    if workspace is True:
+        need = ne_circconv_workspace(N, M, fused)
+        return torch.empty((max(need, 8) // 8,), dtype=torch.int64, device=device) if need else None
+    return workspace or None
+
+
 def ne_lsb_circconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,
-                    out: torch.Tensor | None = None) -> torch.Tensor:
+                    out: torch.Tensor | None = None, workspace=True) -> torch.Tensor:
     """eps: [M, N] int64, g: [N] int8 -> delta [M, N] int64."""
     M, N = eps.shape
     if g.shape != (N,) or M != p.M:
         raise ValueError("shape mismatch")
     if out is None:
         out = torch.empty_like(eps)
+    ws = _conv_ws(workspace, N, M, False, eps.device)
     _ok(lib().ne_lsb_circconv(_dev(eps, "eps", torch.int64), eps_bits, _dev(g, "g", torch.int8),
-                              _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
+                              _dev(out, "out", torch.int64), N, ctypes.byref(p), _opt(ws, "ws", None),
+                              ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
         "ne_lsb_circconv")
     return out
 
@@ -355,7 +370,8 @@ def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None 
 
 def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
                       out_dtype=torch.int64, out: torch.Tensor | None = None,
-                      flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+                      flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None,
+                      workspace=True):
     """c: [M, N] int8/int32/int64, g: [N] int8 -> (d_hat [M, N], flags [ceil(N/32)], n_bad)."""
     M, N = c.shape
     if M != p.M or g.shape != (N,):
@@ -370,10 +386,13 @@ def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
         flags = None
     if n_bad is None:
         n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    ws = _conv_ws(workspace, N, M, True, c.device)
     _ok(lib().ne_circconv_fused(_dev(c, "c"), _DT[c.dtype], c_bits, _dev(g, "g", torch.int8),
                                 _dev(out, "out", out_dtype), _DT[out_dtype],
                                 _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
-                                N, ctypes.byref(p), _stream()), "ne_circconv_fused")
+                                N, ctypes.byref(p), _opt(ws, "ws", None),
+                                ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
+        "ne_circconv_fused")
     return out, flags, n_bad
 
 

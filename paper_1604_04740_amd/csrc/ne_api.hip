@@ -139,8 +139,31 @@ int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t 
                            hs(stream));
 }
 
+// Validates an optional convolution workspace (NULL: none).
+static int check_conv_ws(const void *ws, int64_t ws_bytes, int64_t need, const void *out,
+                         int64_t out_bytes)
+{
+    if (!ws)
+        return NE_OK;
+    if (ws_bytes < need)
+        return NE_EINVAL;
+    if (overlap(ws, need, out, out_bytes))
+        return NE_EALIAS;
+    if ((uintptr_t)ws % 8)
+        return NE_EALIGN;
+    return NE_OK;
+}
+
+int64_t ne_circconv_workspace(int64_t N, int32_t M, int32_t fused)
+{
+    if (N <= 0 || N > kMaxK || M < 3 || M > kMaxStreamsElementwise)
+        return 0;
+    return conv_split(N, M, fused != 0).bytes;
+}
+
 int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t *delta,
-                    int64_t N, const ne_params_t *p, ne_stream_t stream)
+                    int64_t N, const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                    ne_stream_t stream)
 {
     int rc = check_params(p, kMaxStreamsElementwise);
     if (rc)
@@ -156,8 +179,13 @@ int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64
         return NE_EALIAS;
     if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8)
         return NE_EALIGN;
+    const int64_t need = conv_split(N, p->M, false).bytes;
+    if ((rc = check_conv_ws(workspace, workspace_bytes, need, delta, bytes)) != NE_OK)
+        return rc;
+    if (workspace && (overlap(workspace, need, eps, bytes) || overlap(workspace, need, g, N)))
+        return NE_EALIAS;
     return launch_circconv_eps(eps, ne::digits_for_bits(eps_bits), g, delta, N, p->M,
-                               hs(stream));
+                               need ? workspace : nullptr, hs(stream));
 }
 
 int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
@@ -311,7 +339,7 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
 int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g,
                       void *d_hat, int32_t out_dtype, uint32_t *flags,
                       unsigned long long *n_bad, int64_t N, const ne_params_t *p,
-                      ne_stream_t stream)
+                      void *workspace, int64_t workspace_bytes, ne_stream_t stream)
 {
     int rc = check_params(p, kMaxStreamsFused);
     if (rc)
@@ -335,8 +363,16 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
     if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 ||
         (uintptr_t)n_bad % 8)
         return NE_EALIGN;
+    const int64_t need = conv_split(N, p->M, true).bytes;
+    if ((rc = check_conv_ws(workspace, workspace_bytes, need, d_hat, ob)) != NE_OK)
+        return rc;
+    if (workspace && (overlap(workspace, need, c, N * p->M * c_dtype) ||
+                      overlap(workspace, need, g, N) ||
+                      overlap(workspace, need, flags, ((N + 31) / 32) * 4)))
+        return NE_EALIAS;
     return launch_circconv_fused(c, c_dtype, c_bits, g, d_hat, out_dtype == NE_I64, flags, n_bad,
-                                 N, p->M, p->l, p->r_check, hs(stream));
+                                 N, p->M, p->l, p->r_check, need ? workspace : nullptr,
+                                 hs(stream));
 }
 
 int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,

@@ -1,22 +1,64 @@
 // ne_conv.hip -- launchers of the circular-convolution entry points
 // (device code in ne_conv_impl.h: Toeplitz x Hankel blocks on the int8
-// matrix cores).  One workgroup per block of 1024 outputs; the staged form
-// takes up to eight streams per workgroup (grid y covers the rest).
+// matrix cores).  Without a workspace: one workgroup per block of 1024
+// outputs (the staged form takes up to eight streams per workgroup, grid z
+// covers the rest).  With a workspace: the taps of every block are split
+// over several workgroups so that the launch fills the chip, each writes
+// 64-bit partial sums, and a second kernel adds them and finishes.
 #include "ne_conv_impl.h"
 
 namespace ne {
+
+ConvSplit conv_split(int64_t N, int M, bool fused)
+{
+    ConvSplit c{};
+    const int64_t blocks = (N + kCvBlock - 1) / kCvBlock;
+    const int64_t groups = fused ? 1 : (M + kCvMaxSlots - 1) / kCvMaxSlots;
+    const int64_t steps = (N + kCvStep - 1) / kCvStep;
+    const int64_t target = 256; // workgroups: about one per compute unit
+    int64_t S = (target + blocks * groups - 1) / (blocks * groups);
+    if (S > steps)
+        S = steps;
+    if (S <= 1 || N <= 0)
+        return c;
+    const int64_t per = (steps + S - 1) / S; // steps per split
+    c.KC = (int)(per * kCvStep);
+    c.S = (int)((steps + per - 1) / per);
+    c.bytes = (int64_t)c.S * M * blocks * kCvBlock * 8;
+    return c;
+}
+
 namespace {
 
 template <int M>
-int launch_fused_m(const ConvJob &J, unsigned blocks, hipStream_t s)
+int launch_fused_m(const ConvJob &J, unsigned blocks, const ConvSplit &sp, uint64_t *ws,
+                   hipStream_t s)
 {
+    if (sp.S > 1) {
+        k_conv_part<M, true><<<dim3(blocks, sp.S, 1), kCvThreads, 0, s>>>(J, ws, sp.KC, M);
+        if (launch_status())
+            return NE_ELAUNCH;
+        k_conv_reduce<M, true><<<(unsigned)((J.N + 255) / 256), 256, 0, s>>>(
+            J, ws, sp.S, (int64_t)blocks * kCvBlock);
+        return launch_status();
+    }
     k_conv_fused<M><<<blocks, kCvThreads, 0, s>>>(J);
     return launch_status();
 }
 
 template <int G>
-int launch_staged_g(const ConvJob &J, unsigned blocks, unsigned groups, hipStream_t s)
+int launch_staged_g(const ConvJob &J, unsigned blocks, unsigned groups, const ConvSplit &sp,
+                    uint64_t *ws, hipStream_t s)
 {
+    if (sp.S > 1) {
+        k_conv_part<G, false><<<dim3(blocks, sp.S, groups), kCvThreads, 0, s>>>(J, ws, sp.KC,
+                                                                                J.M);
+        if (launch_status())
+            return NE_ELAUNCH;
+        k_conv_reduce<1, false><<<(unsigned)((J.N + 255) / 256), 256, 0, s>>>(
+            J, ws, sp.S, (int64_t)blocks * kCvBlock);
+        return launch_status();
+    }
     k_conv_staged<G><<<dim3(blocks, groups), kCvThreads, 0, s>>>(J);
     return launch_status();
 }
@@ -24,8 +66,9 @@ int launch_staged_g(const ConvJob &J, unsigned blocks, unsigned groups, hipStrea
 } // namespace
 
 int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
-                        int64_t N, int M, hipStream_t s)
+                        int64_t N, int M, void *ws, hipStream_t s)
 {
+    const ConvSplit sp = ws ? conv_split(N, M, false) : ConvSplit{};
     ConvJob J{};
     J.x = eps;
     J.x_dtype = NE_I64;
@@ -36,25 +79,28 @@ int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t
     J.N = N;
     J.M = M;
     const unsigned blocks = (unsigned)((N + kCvBlock - 1) / kCvBlock);
+    uint64_t *w = (uint64_t *)ws;
     switch (M) {
-    case 3: return launch_staged_g<3>(J, blocks, 1, s);
-    case 4: return launch_staged_g<4>(J, blocks, 1, s);
-    case 5: return launch_staged_g<5>(J, blocks, 1, s);
-    case 6: return launch_staged_g<6>(J, blocks, 1, s);
-    case 7: return launch_staged_g<7>(J, blocks, 1, s);
-    case 8: return launch_staged_g<8>(J, blocks, 1, s);
+    case 3: return launch_staged_g<3>(J, blocks, 1, sp, w, s);
+    case 4: return launch_staged_g<4>(J, blocks, 1, sp, w, s);
+    case 5: return launch_staged_g<5>(J, blocks, 1, sp, w, s);
+    case 6: return launch_staged_g<6>(J, blocks, 1, sp, w, s);
+    case 7: return launch_staged_g<7>(J, blocks, 1, sp, w, s);
+    case 8: return launch_staged_g<8>(J, blocks, 1, sp, w, s);
     default:
         if (M > 8 && M <= kMaxStreamsElementwise)
-            return launch_staged_g<kCvMaxSlots>(J, blocks,
-                                                (unsigned)((M + kCvMaxSlots - 1) / kCvMaxSlots), s);
+            return launch_staged_g<kCvMaxSlots>(
+                J, blocks, (unsigned)((M + kCvMaxSlots - 1) / kCvMaxSlots), sp, w, s);
         return NE_EUNSUP;
     }
 }
 
 int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, void *dhat,
                           int out64, uint32_t *flags, unsigned long long *n_bad, int64_t N, int M,
-                          int l, int r, hipStream_t s)
+                          int l, int r, void *ws, hipStream_t s)
 {
+    const ConvSplit sp = ws ? conv_split(N, M, true) : ConvSplit{};
+    uint64_t *w = (uint64_t *)ws;
     ConvJob J{};
     J.x = c;
     J.x_dtype = c_dtype;
@@ -70,12 +116,12 @@ int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *
     J.r = r;
     const unsigned blocks = (unsigned)((N + kCvBlock - 1) / kCvBlock);
     switch (M) {
-    case 3: return launch_fused_m<3>(J, blocks, s);
-    case 4: return launch_fused_m<4>(J, blocks, s);
-    case 5: return launch_fused_m<5>(J, blocks, s);
-    case 6: return launch_fused_m<6>(J, blocks, s);
-    case 7: return launch_fused_m<7>(J, blocks, s);
-    case 8: return launch_fused_m<8>(J, blocks, s);
+    case 3: return launch_fused_m<3>(J, blocks, sp, w, s);
+    case 4: return launch_fused_m<4>(J, blocks, sp, w, s);
+    case 5: return launch_fused_m<5>(J, blocks, sp, w, s);
+    case 6: return launch_fused_m<6>(J, blocks, sp, w, s);
+    case 7: return launch_fused_m<7>(J, blocks, sp, w, s);
+    case 8: return launch_fused_m<8>(J, blocks, sp, w, s);
     default: return NE_EUNSUP;
     }
 }

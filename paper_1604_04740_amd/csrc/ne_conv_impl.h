@@ -106,9 +106,10 @@ __device__ __forceinline__ int cv_ring_off(int64_t v)
     return ((c ^ ((c >> 4) & 1)) << 4) | (int)(v & 15);
 }
 
-__device__ __forceinline__ int64_t cv_mod(int64_t a, int64_t N)
+// a mod N in [0, N) for |a| < 2^31 (N <= 131071, so every index here fits).
+__device__ __forceinline__ int cv_mod(int a, int N)
 {
-    int64_t m = a % N;
+    const int m = a % N;
     return m < 0 ? m + N : m;
 }
 
@@ -116,12 +117,10 @@ __device__ __forceinline__ int64_t cv_mod(int64_t a, int64_t N)
 template <int G>
 struct CvA {
     int64_t val[G];
-    int64_t v;
-    __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int64_t t0,
-                                         int64_t v_)
+    int v;
+    __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int idx, int v_)
     {
         v = v_;
-        const int64_t idx = cv_mod(t0 - v, J.N);
 #pragma unroll
         for (int s = 0; s < G; ++s)
             val[s] = stream[s] >= 0 ? cv_load(J.x, J.x_dtype, (int64_t)stream[s] * J.N + idx) : 0;
@@ -139,12 +138,12 @@ struct CvA {
 struct CvG {
     uint32_t w[8];
     int p;
-    int64_t i0;
-    __device__ __forceinline__ void load(const ConvJob &J, int64_t I, int tid)
+    int i0;
+    __device__ __forceinline__ void load(const ConvJob &J, int I, int tid)
     {
         p = tid >> 3;
         i0 = I + 32 * (tid & 7);
-        const int64_t N = J.N, s = i0 + p;
+        const int N = (int)J.N, s = i0 + p;
         if (i0 + 32 <= N && s + 36 <= N) {
             // g[s .. s+31] from nine aligned dwords inside g
             const uintptr_t a = (uintptr_t)(J.g + s);
@@ -159,14 +158,14 @@ struct CvG {
                 w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], sh);
         } else {
             // wrap-around or past the last tap: byte by byte
+            int j = cv_mod(s, N);
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 uint32_t x = 0;
                 for (int b = 0; b < 4; ++b) {
-                    const int64_t i = i0 + 4 * k + b;
-                    const uint32_t byte =
-                        i < N ? (uint32_t)(uint8_t)J.g[cv_mod(i + p, N)] : 0u;
+                    const uint32_t byte = i0 + 4 * k + b < N ? (uint32_t)(uint8_t)J.g[j] : 0u;
                     x |= byte << (8 * b);
+                    j = j + 1 == N ? 0 : j + 1;
                 }
                 w[k] = x;
             }
@@ -180,10 +179,23 @@ struct CvG {
     }
 };
 
-// One block of 1024 outputs of G slots.  FUSED: G == M, disentangle and
-// check in the epilogue.  lds: cv_lds_bytes(G) bytes, 16-byte aligned.
+// Stream held by slot s: fused, stream (r + s) mod M (slot 0 is the one the
+// check rebuilds); staged, stream s0 + s, or -1 past the last stream.
 template <int G, bool FUSED>
-__device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
+__device__ __forceinline__ void cv_streams(const ConvJob &J, int (&stream)[G])
+{
+#pragma unroll
+    for (int s = 0; s < G; ++s)
+        stream[s] = FUSED ? (J.r + s) % J.M : (J.s0 + s < J.M ? J.s0 + s : -1);
+}
+
+// Taps [Ia, Ib) (multiples of 256, Ib <= the tap count rounded up to 256)
+// of the block of 1024 outputs starting at t0, every digit pass, folded
+// into red[slot][position] (uint64, mod 2^64).  Ends after a barrier, with
+// red complete.  lds: cv_lds_bytes(G) bytes, 16-byte aligned.
+template <int G, bool FUSED>
+__device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, int Ia, int Ib,
+                                                const int (&stream)[G], int8_t *lds)
 {
     constexpr int CH = FUSED ? 2 * G : G; // accumulator sets
     int8_t *rings = lds;
@@ -192,18 +204,14 @@ __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int64_t N = J.N, t0 = block * kCvBlock;
-    const int64_t Np = (N + 31) & ~(int64_t)31;
-    const int steps = (int)((Np + kCvStep - 1) / kCvStep);
-    int stream[G];
-#pragma unroll
-    for (int s = 0; s < G; ++s)
-        stream[s] = FUSED ? (J.r + s) % J.M : (J.s0 + s < J.M ? J.s0 + s : -1);
+    const int Ni = (int)J.N, t0i = (int)t0, step_mod = kCvStep % Ni;
+    const int Np = (Ni + 31) & ~31;
+    const int steps = (Ib - Ia) / kCvStep;
+    const int a = lane & 31, h = lane >> 5;
 
     for (int i = tid; i < G * kCvBlock; i += kCvThreads)
         red[i] = 0;
 
-    const int a = lane & 31, h = lane >> 5;
     for (int d = 0; d < J.digits; ++d) {
         cv16i acc[CH];
 #pragma unroll
@@ -212,34 +220,41 @@ __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8
             for (int e = 0; e < 16; ++e)
                 acc[q][e] = 0;
 
-        // prologue: ring bytes v in [-992, 256) and g taps [0, 256)
+        // prologue: ring bytes v in [Ia - 992, Ia + 256) and g taps [Ia, Ia + 256)
         for (int k = tid; k < 992 + kCvStep; k += kCvThreads) {
             CvA<G> st;
-            st.load(J, stream, t0, (int64_t)k - 992);
+            const int v = Ia - 992 + k;
+            st.load(J, stream, cv_mod(t0i - v, Ni), v);
             st.store(rings, d);
         }
+        // ring coordinate v = Ia + 256 (j + 1) + tid of step j's prefetch,
+        // and its input index (t0 - v) mod N, advanced by -256 mod N per step
+        int pidx = cv_mod(t0i - Ia - kCvStep - tid, Ni);
         {
             CvG sg;
-            sg.load(J, 0, tid);
+            sg.load(J, Ia, tid);
             sg.store(gc);
         }
         __syncthreads();
 
         for (int j = 0; j < steps; ++j) {
-            const int64_t I = (int64_t)j * kCvStep;
+            const int I = Ia + j * kCvStep;
             const bool more = j + 1 < steps;
             CvA<G> na;
             CvG ng;
             if (more) {
-                na.load(J, stream, t0, I + kCvStep + tid);
+                na.load(J, stream, pidx, I + kCvStep + tid);
                 ng.load(J, I + kCvStep, tid);
+                pidx -= step_mod;
+                if (pidx < 0)
+                    pidx += Ni;
             }
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                const int64_t i0 = I + 64 * wave + 32 * kk;
+                const int i0 = I + 64 * wave + 32 * kk;
                 if (i0 < Np) {
                     const cv4i B = *(const cv4i *)(gc + a * kCvGStride +
-                                                   (int)((i0 + 16 * h) & (kCvGRing - 1)));
+                                                   ((i0 + 16 * h) & (kCvGRing - 1)));
                     cv4i A[G];
 #pragma unroll
                     for (int s = 0; s < G; ++s)
@@ -278,47 +293,71 @@ __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8
             }
         __syncthreads();
     }
+}
 
-    // epilogue: four groups of 256 consecutive outputs
+// Finish one output position t of the fused form from the M delta words
+// of its slots: disentangle, check, store, and the wavefront's flag words
+// (the 64 lanes of a wavefront hold 64 consecutive positions starting at a
+// multiple of 64).
+template <int M>
+__device__ __forceinline__ void conv_finish(const ConvJob &J, const int (&stream)[M], int64_t t,
+                                            int64_t (&dd)[M])
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t N = J.N;
+    const bool valid = t < N;
+    int64_t o[M];
+    const bool flag = disentangle_rot<M>(dd, J.l, o) && valid;
+    if (valid) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            const int64_t idx = (int64_t)stream[s] * N + t;
+            if (J.out64)
+                ((int64_t *)J.out)[idx] = o[s];
+            else
+                ((int32_t *)J.out)[idx] = (int32_t)o[s];
+        }
+    }
+    const uint64_t mask = __ballot(flag);
+    const int64_t words = (N + 31) / 32, w0 = (t - lane) / 32;
+    if (J.flags) {
+        if (lane == 0 && w0 < words)
+            J.flags[w0] = (uint32_t)mask;
+        if (lane == 32 && w0 + 1 < words)
+            J.flags[w0 + 1] = (uint32_t)(mask >> 32);
+    }
+    if (J.n_bad && lane == 0 && mask)
+        atomicAdd(J.n_bad, (unsigned long long)__popcll(mask));
+}
+
+// One whole block of 1024 outputs (all taps) in one workgroup.  FUSED:
+// G == M, disentangle and check; staged: write delta.
+template <int G, bool FUSED>
+__device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
+{
+    int stream[G];
+    cv_streams<G, FUSED>(J, stream);
+    const int64_t t0 = block * kCvBlock;
+    const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
+    conv_accumulate<G, FUSED>(J, t0, 0, taps, stream, lds);
+    const auto *red = (const unsigned long long *)(lds + G * kCvRing + 32 * kCvGStride);
+    const int tid = threadIdx.x;
 #pragma unroll 1
     for (int q = 0; q < kCvBlock / kCvThreads; ++q) {
         const int pos = q * kCvThreads + tid;
         const int64_t t = t0 + pos;
-        const bool valid = t < N;
         if constexpr (FUSED) {
-            int64_t dd[G], o[G];
+            int64_t dd[G];
 #pragma unroll
             for (int s = 0; s < G; ++s)
                 dd[s] = (int64_t)red[s * kCvBlock + pos];
-            const bool flag = disentangle_rot<G>(dd, J.l, o) && valid;
-            if (valid) {
+            conv_finish<G>(J, stream, t, dd);
+        } else if (t < J.N) {
 #pragma unroll
-                for (int s = 0; s < G; ++s) {
-                    const int64_t idx = (int64_t)stream[s] * N + t;
-                    if (J.out64)
-                        ((int64_t *)J.out)[idx] = o[s];
-                    else
-                        ((int32_t *)J.out)[idx] = (int32_t)o[s];
-                }
-            }
-            const uint64_t mask = __ballot(flag);
-            const int64_t words = (N + 31) / 32, w0 = (t0 + q * kCvThreads + 64 * wave) / 32;
-            if (J.flags) {
-                if (lane == 0 && w0 < words)
-                    J.flags[w0] = (uint32_t)mask;
-                if (lane == 32 && w0 + 1 < words)
-                    J.flags[w0 + 1] = (uint32_t)(mask >> 32);
-            }
-            if (J.n_bad && lane == 0 && mask)
-                atomicAdd(J.n_bad, (unsigned long long)__popcll(mask));
-        } else {
-            if (valid) {
-#pragma unroll
-                for (int s = 0; s < G; ++s)
-                    if (stream[s] >= 0)
-                        ((int64_t *)J.out)[(int64_t)stream[s] * N + t] =
-                            (int64_t)red[s * kCvBlock + pos];
-            }
+            for (int s = 0; s < G; ++s)
+                if (stream[s] >= 0)
+                    ((int64_t *)J.out)[(int64_t)stream[s] * J.N + t] =
+                        (int64_t)red[s * kCvBlock + pos];
         }
     }
 }
@@ -336,6 +375,63 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_staged(ConvJob J)
     __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
     J.s0 = (int)blockIdx.y * G;
     conv_block<G, false>(J, blockIdx.x, lds);
+}
+
+// Split taps: workgroup (block, z, group) accumulates taps [z KC, (z+1) KC)
+// and writes its 64-bit partial sums to ws[z][stream or slot][position]
+// (positions padded to whole blocks: Nb = blocks * 1024).
+template <int G, bool FUSED>
+__global__ __launch_bounds__(kCvThreads) void k_conv_part(ConvJob J, uint64_t *ws, int KC,
+                                                          int slots)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
+    J.s0 = (int)blockIdx.z * G;
+    int stream[G];
+    cv_streams<G, FUSED>(J, stream);
+    const int64_t t0 = (int64_t)blockIdx.x * kCvBlock;
+    const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
+    const int z = blockIdx.y, Ia = z * KC, Ib = Ia + KC < taps ? Ia + KC : taps;
+    conv_accumulate<G, FUSED>(J, t0, Ia, Ib, stream, lds);
+    const auto *red = (const unsigned long long *)(lds + G * kCvRing + 32 * kCvGStride);
+    const int64_t Nb = (int64_t)gridDim.x * kCvBlock;
+    for (int i = threadIdx.x; i < G * kCvBlock; i += kCvThreads) {
+        const int s = i / kCvBlock, pos = i % kCvBlock;
+        const int row = FUSED ? s : stream[s];
+        if (row >= 0)
+            ws[((int64_t)z * slots + row) * Nb + t0 + pos] = red[i];
+    }
+}
+
+// Sum the partials of every split and finish: fused, disentangle and check
+// (M == slots); staged, write delta.  One thread per position.
+template <int M, bool FUSED>
+__global__ __launch_bounds__(256) void k_conv_reduce(const ConvJob J, const uint64_t *ws, int S,
+                                                     int64_t Nb)
+{
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if constexpr (FUSED) {
+        int stream[M];
+        cv_streams<M, true>(J, stream);
+        int64_t dd[M];
+        const int64_t tc = t < Nb ? t : 0;
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            uint64_t v = 0;
+            for (int z = 0; z < S; ++z)
+                v += ws[((int64_t)z * M + s) * Nb + tc];
+            dd[s] = (int64_t)v;
+        }
+        conv_finish<M>(J, stream, t, dd);
+    } else {
+        if (t >= J.N)
+            return;
+        for (int m = 0; m < J.M; ++m) {
+            uint64_t v = 0;
+            for (int z = 0; z < S; ++z)
+                v += ws[((int64_t)z * J.M + m) * Nb + t];
+            ((int64_t *)J.out)[(int64_t)m * J.N + t] = (int64_t)v;
+        }
+    }
 }
 
 } // namespace

@@ -51,11 +51,18 @@ int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *fl
                      hipStream_t s);
 
 // ---- circular convolution (ne_conv.hip) ----
+// Split of the taps over workgroups when a workspace is given: S splits of
+// KC taps each, bytes of 64-bit partial sums (S <= 1: no split).
+struct ConvSplit {
+    int S, KC;
+    int64_t bytes;
+};
+ConvSplit conv_split(int64_t N, int M, bool fused);
 int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t *delta,
-                        int64_t N, int M, hipStream_t s);
+                        int64_t N, int M, void *ws, hipStream_t s);
 int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, void *dhat,
                           int out64, uint32_t *flags, unsigned long long *n_bad, int64_t N, int M,
-                          int l, int r, hipStream_t s);
+                          int l, int r, void *ws, hipStream_t s);
 
 // Grid size for grid-stride element-wise kernels.
 inline unsigned grid_for(int64_t work, int threads)

@@ -95,3 +95,28 @@ def test_range_rejection_fused(ne):
     rc = L.ne_gemm_fused(ctypes.c_void_p(16), ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30),
                          4, None, None, 4, K_bad, 4, ctypes.byref(p_small), None, None)
     assert rc == -2
+
+
+def test_conv_workspace_size_and_rejection(ne):
+    """The split of the taps the workspace query reports, and a workspace
+    smaller than that is rejected before any launch."""
+    L = ne.lib()
+    # 16 blocks of 1024 outputs, 64 steps of 256 taps: 16 splits of 4 steps
+    assert L.ne_circconv_workspace(16384, 3, 1) == 16 * 3 * 16384 * 8
+    # one block, 4 steps: 4 splits of one step
+    assert L.ne_circconv_workspace(1000, 3, 1) == 4 * 3 * 1024 * 8
+    # staged with 11 streams: two groups of workgroups per block
+    assert L.ne_circconv_workspace(1000, 11, 0) == 4 * 11 * 1024 * 8
+    # a single step (N <= 256) is never split; invalid sizes report 0
+    assert L.ne_circconv_workspace(200, 3, 1) == 0
+    assert L.ne_circconv_workspace(0, 3, 1) == 0 and L.ne_circconv_workspace(10, 2, 1) == 0
+    p = ne.ne_params_default(3)
+    need = L.ne_circconv_workspace(1000, 3, 1)
+    c, g, d, ws = (ctypes.c_void_p(a) for a in (1 << 20, 2 << 20, 3 << 20, 4 << 20))
+    rc = L.ne_circconv_fused(c, 8, 11, g, d, 8, None, None, 1000, ctypes.byref(p), ws, need - 8,
+                             None)
+    assert rc == -1
+    rc = L.ne_circconv_fused(c, 8, 11, g, d, 8, None, None, 1000, ctypes.byref(p), d, need, None)
+    assert rc == -3  # overlaps d_hat
+    rc = L.ne_lsb_circconv(c, 40, g, d, 1000, ctypes.byref(p), ws, need - 8, None)
+    assert rc == -1

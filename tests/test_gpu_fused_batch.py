@@ -47,6 +47,9 @@ def test_circconv_fused(ne, orc, M, N):
     dh32, _, _ = ne.ne_circconv_fused(_t(c.astype(np.int32)), _t(g), p, c_bits=11,
                                       out_dtype=torch.int32)
     assert np.array_equal(_h(dh32), ref["dhat"].astype(np.int32))
+    # without a workspace: one workgroup per block of 1024 outputs
+    dh, fl, nb = ne.ne_circconv_fused(_t(c), _t(g), p, c_bits=11, workspace=None)
+    assert np.array_equal(_h(dh), ref["dhat"]) and int(nb.item()) == 0
 
 
 @pytest.mark.parametrize("M,N,cdt,bits", [(6, 2500, np.int8, 8), (3, 700, np.int32, 20),

@@ -205,8 +205,9 @@ def test_circconv_any_words(ne, orc, M, N, bits):
     x = (raw >> np.int64(64 - bits)).reshape(M, N)  # uniform in [-2^(bits-1), 2^(bits-1))
     g = ne_synth.uniform_int(850 + M + N, 3, (N,), -128, 128).astype(np.int8)
     ref = np.stack([orc.circconv(x[m], g.astype(np.int64)) for m in range(M)])
-    got = ne.ne_lsb_circconv(_t(x), bits, _t(g), p)
-    assert np.array_equal(_h(got), ref)
+    for ws in (True, None):  # split taps over workgroups, and one workgroup per block
+        got = ne.ne_lsb_circconv(_t(x), bits, _t(g), p, workspace=ws)
+        assert np.array_equal(_h(got), ref), ws
 
 
 # ------------------------------------------------------------- fused GEMM
