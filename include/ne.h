@@ -286,7 +286,7 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
                       void *workspace, int64_t workspace_bytes, ne_stream_t stream);
 
 /*
- * Fused permutation + scaling + addition, one launch (section II, op in
+ * Fused permutation + scaling + addition (section II, op in
  * {permutation, x, +}, with the constant self-entangled per the footnote of
  * section III-A): for every position n the M inputs at perm[n] are
  * entangled, delta = scale[n] eps + (2^l + 1) add[n], then disentangled and
@@ -295,11 +295,26 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
  *   c          device, [M][N] of c_dtype;  perm device [N] int32 (clamped);
  *   scale/add  device [N] int64 or NULL;   d_hat device [M][N] out_dtype;
  *   flags      device [ceil(N/32)] or NULL; n_bad device counter or NULL.
+ *   workspace  device scratch of ne_permute_workspace(N, M, c_dtype) bytes,
+ *              or NULL.  With it a first launch copies the inputs into rows
+ *              (the M inputs of a position side by side, 64-bit padded) so
+ *              that each position's random gather touches one cache line
+ *              instead of M; with NULL one launch gathers from c directly.
+ *              Caller-owned, 8-byte aligned, no overlap with the other
+ *              arguments, contents on entry irrelevant; too small is
+ *              NE_EINVAL.
  */
 int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
                            const int64_t *scale, const int64_t *add, void *d_hat,
                            int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                           int64_t N, const ne_params_t *p, ne_stream_t stream);
+                           int64_t N, const ne_params_t *p, void *workspace,
+                           int64_t workspace_bytes, ne_stream_t stream);
+
+/*
+ * Workspace bytes of ne_permute_scale_fused: N * ceil(M * c_dtype / 8) * 8;
+ * 0 for invalid sizes.
+ */
+int64_t ne_permute_workspace(int64_t N, int32_t M, int32_t c_dtype);
 
 /* ------------------------------------------------------------------ batch */
 

@@ -20,7 +20,7 @@ __all__ = [
     "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
-    "ne_circconv_fused", "ne_circconv_workspace", "ne_permute_scale_fused", "Inject", "Problem", "Batch", "ne_batch_plan",
+    "ne_circconv_fused", "ne_circconv_workspace", "ne_permute_scale_fused", "ne_permute_workspace", "Inject", "Problem", "Batch", "ne_batch_plan",
     "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
 
@@ -97,7 +97,8 @@ def lib():
             "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp,
                                    _i64, _vp], ctypes.c_int),
             "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
-                                        _vp], ctypes.c_int),
+                                        _vp, _i64, _vp], ctypes.c_int),
+            "ne_permute_workspace": ([_i64, _i32, _i32], _i64),
             "ne_batch_plan": ([ctypes.POINTER(_Problem), _i32, ctypes.POINTER(_Tuning), _vp, _i64,
                                ctypes.POINTER(_i64), ctypes.POINTER(_vp)], ctypes.c_int),
             "ne_batch_run": ([_vp, _vp], ctypes.c_int),
@@ -193,6 +194,10 @@ def ne_lsb_gemm(eps: torch.Tensor, eps_bits: int, Gt: torch.Tensor, p: Params,
                           _dev(out, "out", torch.int64), n, K, N, ctypes.byref(p), _stream()),
         "ne_lsb_gemm")
     return out
+
+
+def ne_permute_workspace(N: int, M: int, c_dtype: torch.dtype) -> int:
+    return int(lib().ne_permute_workspace(N, M, _DT[c_dtype]))
 
 
 def ne_circconv_workspace(N: int, M: int, fused: bool) -> int:
@@ -399,8 +404,9 @@ def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
 def ne_permute_scale_fused(c: torch.Tensor, perm: torch.Tensor, scale: torch.Tensor | None,
                            add: torch.Tensor | None, p: Params, out_dtype=torch.int64,
                            out: torch.Tensor | None = None, flags: bool | torch.Tensor = True,
-                           n_bad: torch.Tensor | None = None):
-    """c: [M, N]; perm [N] int32; scale/add [N] int64 or None -> (d_hat, flags, n_bad)."""
+                           n_bad: torch.Tensor | None = None, workspace=True):
+    """c: [M, N]; perm [N] int32; scale/add [N] int64 or None -> (d_hat, flags, n_bad).
+    workspace=True allocates the row copy the library gathers from; None: direct gather."""
     M, N = c.shape
     if M != p.M or perm.shape != (N,):
         raise ValueError("shape mismatch")
@@ -414,11 +420,17 @@ def ne_permute_scale_fused(c: torch.Tensor, perm: torch.Tensor, scale: torch.Ten
         flags = None
     if n_bad is None:
         n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    if workspace is True:
+        need = int(lib().ne_permute_workspace(N, M, _DT[c.dtype]))
+        workspace = torch.empty((need // 8,), dtype=torch.int64, device=c.device)
+    ws = workspace if workspace is not None and workspace is not False else None
     _ok(lib().ne_permute_scale_fused(_dev(c, "c"), _DT[c.dtype], _dev(perm, "perm", torch.int32),
                                      _opt(scale, "scale", torch.int64), _opt(add, "add", torch.int64),
                                      _dev(out, "out", out_dtype), _DT[out_dtype],
                                      _opt(flags, "flags", torch.int32),
                                      _dev(n_bad, "n_bad", torch.int64), N, ctypes.byref(p),
+                                     _opt(ws, "workspace", None),
+                                     ws.numel() * ws.element_size() if ws is not None else 0,
                                      _stream()), "ne_permute_scale_fused")
     return out, flags, n_bad
 

@@ -375,10 +375,19 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
                                  hs(stream));
 }
 
+int64_t ne_permute_workspace(int64_t N, int32_t M, int32_t c_dtype)
+{
+    if (N <= 0 || N > 0x7fffffff || M < 3 || M > kMaxStreamsElementwise ||
+        (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64))
+        return 0;
+    return permute_rows_bytes(N, M, c_dtype);
+}
+
 int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
                            const int64_t *scale, const int64_t *add, void *d_hat,
                            int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                           int64_t N, const ne_params_t *p, ne_stream_t stream)
+                           int64_t N, const ne_params_t *p, void *workspace,
+                           int64_t workspace_bytes, ne_stream_t stream)
 {
     int rc = check_params(p, kMaxStreamsElementwise);
     if (rc)
@@ -398,8 +407,21 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
     if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)perm % 4 ||
         (uintptr_t)scale % 8 || (uintptr_t)add % 8 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
         return NE_EALIGN;
+    if (workspace) {
+        const int64_t need = permute_rows_bytes(N, p->M, c_dtype);
+        if (workspace_bytes < need)
+            return NE_EINVAL;
+        if (overlap(workspace, need, c, N * p->M * c_dtype) || overlap(workspace, need, d_hat, ob) ||
+            overlap(workspace, need, perm, N * 4) || overlap(workspace, need, scale, N * 8) ||
+            overlap(workspace, need, add, N * 8) ||
+            overlap(workspace, need, flags, ((N + 31) / 32) * 4))
+            return NE_EALIAS;
+        if ((uintptr_t)workspace % 8)
+            return NE_EALIGN;
+    }
     return launch_permute_scale_fused(c, c_dtype, perm, scale, add, d_hat, out_dtype == NE_I64,
-                                      flags, n_bad, N, p->M, p->l, p->r_check, hs(stream));
+                                      flags, n_bad, N, p->M, p->l, p->r_check, workspace,
+                                      hs(stream));
 }
 
 } // extern "C"

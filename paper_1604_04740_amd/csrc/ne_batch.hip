@@ -3,19 +3,21 @@
 //
 // Host side (setup, not graph-capturable): ne_batch_plan turns a problem
 // list into work items -- one per GEMM output tile, one per 1024-position
-// convolution block, one per permute/scale chunk -- orders them
-// longest-first by a cost estimate (so the long items start early and the
-// short ones fill the tail), and writes the problem table and item list
-// into a caller-provided device buffer.  ne_batch_autotune times the
-// candidate tile choices of every (operation, M, size-class) bucket on the
-// device and returns the fastest per bucket.
+// convolution block, two per permute/scale chunk (copy of the inputs into
+// rows, then the gather) -- orders them longest-first by a cost estimate
+// (so the long items start early and the short ones fill the tail), and
+// writes the problem table, the item list and room for the row copies into
+// a caller-provided device buffer.  ne_batch_autotune times the candidate
+// tile choices of every (operation, M, size-class) bucket on the device and
+// returns the fastest per bucket.
 //
 // Device side: ne_batch_run launches a counter reset and the persistent
-// kernel (grid = one workgroup per CU).  Every workgroup takes the next item
-// from a global atomic counter and runs the fused tile function of that
-// item's operation; it exits when the counter passes the item count, so the
-// grid always drains.  Both launches are plain kernels (no memset nodes),
-// so ne_batch_run can be captured in a HIP graph and replayed.
+// kernel twice (grid = one workgroup per CU): phase 0 runs every GEMM tile,
+// convolution block and row copy, phase 1 the permutation gathers that read
+// those rows.  Every workgroup takes the next item of its phase from a
+// global atomic counter; it exits when the counter passes the item count,
+// so the grid always drains.  All launches are plain kernels (no memset
+// nodes), so ne_batch_run can be captured in a HIP graph and replayed.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -44,15 +46,21 @@ struct DevProblem {
     void *dhat;
     uint32_t *flags;
     unsigned long long *n_bad;
+    uint64_t *rows; // permutation: row copy of the inputs (in the table)
 };
 
+// kind 0: the item of its operation; kind 1: a chunk of a permutation's
+// row copy (first phase; the gathers run in the second).
 struct DevItem {
-    int32_t problem, a, b, pad;
+    int32_t problem, a, b, kind;
 };
 
+// Two phases, one launch each: the second (permutation gathers) reads the
+// row copies the first wrote.  Phase p's items are items[first[p] ..).
 struct DevHeader {
-    unsigned int counter;
-    int32_t n_items, n_problems, pad;
+    unsigned int counter[2];
+    int32_t n_items[2], first[2];
+    int32_t n_problems, pad;
     int64_t problems_off, items_off;
 };
 
@@ -115,7 +123,10 @@ __device__ __forceinline__ void run_conv_m(const DevProblem &P, int block, int8_
     J.M = M;
     J.l = P.l;
     J.r = P.r;
-    conv_block<M, true>(J, block, lds);
+    // above four streams the two products of every slot take two passes:
+    // this kernel also holds the GEMM tiles, and 2M accumulator sets for
+    // M > 4 would push it into spilling
+    conv_block<M, true, (M > 4)>(J, block, lds);
 }
 
 __device__ __forceinline__ void run_conv(const DevProblem &P, int block, int8_t *lds)
@@ -132,23 +143,28 @@ __device__ __forceinline__ void run_conv(const DevProblem &P, int block, int8_t 
 }
 
 template <int M>
-__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk)
+__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk, bool pack)
 {
     const int64_t first = (int64_t)chunk * P.chunk;
     const int64_t last = first + P.chunk < P.N ? first + P.chunk : P.N;
-    perm_fused_range<M, int8_t>((const int8_t *)P.c, P.perm, P.scale, P.add, P.dhat, P.out64,
-                                P.flags, P.n_bad, P.N, P.l, P.r, first, last, 0, kBatchThreads);
+    if (pack)
+        perm_pack_range<M, int8_t>((const int8_t *)P.c, P.rows, P.N, P.r, first, last, 0,
+                                   kBatchThreads);
+    else
+        perm_fused_range<M, int8_t>((const int8_t *)P.c, P.rows, P.perm, P.scale, P.add, P.dhat,
+                                    P.out64, P.flags, P.n_bad, P.N, P.l, P.r, first, last, 0,
+                                    kBatchThreads);
 }
 
-__device__ __forceinline__ void run_perm(const DevProblem &P, int chunk)
+__device__ __forceinline__ void run_perm(const DevProblem &P, int chunk, bool pack)
 {
     switch (P.M) {
-    case 3: run_perm_m<3>(P, chunk); return;
-    case 4: run_perm_m<4>(P, chunk); return;
-    case 5: run_perm_m<5>(P, chunk); return;
-    case 6: run_perm_m<6>(P, chunk); return;
-    case 7: run_perm_m<7>(P, chunk); return;
-    case 8: run_perm_m<8>(P, chunk); return;
+    case 3: run_perm_m<3>(P, chunk, pack); return;
+    case 4: run_perm_m<4>(P, chunk, pack); return;
+    case 5: run_perm_m<5>(P, chunk, pack); return;
+    case 6: run_perm_m<6>(P, chunk, pack); return;
+    case 7: run_perm_m<7>(P, chunk, pack); return;
+    case 8: run_perm_m<8>(P, chunk, pack); return;
     default: return;
     }
 }
@@ -158,19 +174,23 @@ static_assert(dma_lds_bytes<FusedV<4, 256>, kGemmBK, kGemmStages>() <= kBatchLds
 static_assert(dma_lds_bytes<FusedV<8, 128>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
 static_assert(cv_lds_bytes(kCvMaxSlots) <= kBatchLds, "LDS");
 
-__global__ void k_batch_reset(DevHeader *h) { h->counter = 0u; }
+__global__ void k_batch_reset(DevHeader *h)
+{
+    h->counter[0] = 0u;
+    h->counter[1] = 0u;
+}
 
-__global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table)
+__global__ __launch_bounds__(kBatchThreads, 1) void k_batch(uint8_t *table, int phase)
 {
     __shared__ __attribute__((aligned(1024))) int8_t lds[kBatchLds];
     __shared__ int item_sh;
     auto *h = (DevHeader *)table;
     const auto *problems = (const DevProblem *)(table + h->problems_off);
-    const auto *items = (const DevItem *)(table + h->items_off);
-    const int n_items = h->n_items;
+    const auto *items = (const DevItem *)(table + h->items_off) + h->first[phase];
+    const int n_items = h->n_items[phase];
     for (;;) {
         if (threadIdx.x == 0)
-            item_sh = (int)atomicAdd(&h->counter, 1u);
+            item_sh = (int)atomicAdd(&h->counter[phase], 1u);
         __syncthreads();
         const int it = item_sh;
         __syncthreads();
@@ -183,7 +203,7 @@ __global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table
         else if (P.op == NE_OP_CONV)
             run_conv(P, im.a, lds);
         else
-            run_perm(P, im.a);
+            run_perm(P, im.a, im.kind == 1);
         __syncthreads(); // the next item reuses the LDS
     }
 }
@@ -207,8 +227,8 @@ int64_t problem_size(const ne_problem_t &p)
 struct BatchPlan {
     void *table;
     int64_t bytes;
-    int n_items;
-    int grid;
+    int n_items[2];
+    int grid[2];
 };
 
 } // namespace ne
@@ -271,7 +291,10 @@ double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
 
 struct Built {
     std::vector<DevProblem> probs;
-    std::vector<DevItem> items;
+    std::vector<DevItem> items; // phase 0 items, then phase 1 items
+    int n0 = 0;
+    std::vector<int64_t> rows_off; // per problem, offset of its row copy (or -1)
+    int64_t rows_bytes = 0;
 };
 
 int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuning, Built &out)
@@ -280,8 +303,10 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
         DevItem it;
         double cost;
     };
-    std::vector<Tmp> tmp;
+    std::vector<Tmp> tmp, tmp2; // phase 0, phase 1
     out.probs.resize(count);
+    out.rows_off.assign(count, -1);
+    out.rows_bytes = 0;
     for (int i = 0; i < count; ++i) {
         const ne_problem_t &q = problems[i];
         ne_params_t p;
@@ -333,32 +358,55 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
             d.chunk = chunk;
             const int chunks = (int)((q.N + chunk - 1) / chunk);
             const double c1 = item_cost(q, 0, chunk);
-            for (int b = 0; b < chunks; ++b)
-                tmp.push_back({{i, b, 0, 0}, c1});
+            out.rows_off[i] = out.rows_bytes;
+            out.rows_bytes += (permute_rows_bytes(q.N, q.M, NE_I8) + 255) / 256 * 256;
+            for (int b = 0; b < chunks; ++b) {
+                tmp.push_back({{i, b, 0, 1}, c1 / 4}); // row copy: streaming
+                tmp2.push_back({{i, b, 0, 0}, c1});
+            }
         }
     }
-    std::stable_sort(tmp.begin(), tmp.end(), [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; });
-    out.items.resize(tmp.size());
+    auto by_cost = [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; };
+    std::stable_sort(tmp.begin(), tmp.end(), by_cost);
+    std::stable_sort(tmp2.begin(), tmp2.end(), by_cost);
+    out.n0 = (int)tmp.size();
+    out.items.resize(tmp.size() + tmp2.size());
     for (size_t i = 0; i < tmp.size(); ++i)
         out.items[i] = tmp[i].it;
+    for (size_t i = 0; i < tmp2.size(); ++i)
+        out.items[tmp.size() + i] = tmp2[i].it;
     return NE_OK;
+}
+
+// Table layout: header | problems | items | (256-aligned) row copies.
+int64_t table_head_bytes(const Built &b)
+{
+    const int64_t h = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem) +
+                      (int64_t)b.items.size() * sizeof(DevItem);
+    return (h + 255) / 256 * 256;
 }
 
 int64_t table_bytes(const Built &b)
 {
-    return kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem) +
-           (int64_t)b.items.size() * sizeof(DevItem);
+    return table_head_bytes(b) + b.rows_bytes;
 }
 
-int upload(const Built &b, void *table_dev)
+int upload(Built &b, void *table_dev)
 {
-    std::vector<uint8_t> host(table_bytes(b), 0);
+    const int64_t head = table_head_bytes(b);
+    std::vector<uint8_t> host(head, 0);
     DevHeader h{};
-    h.counter = 0;
-    h.n_items = (int32_t)b.items.size();
+    h.n_items[0] = b.n0;
+    h.n_items[1] = (int32_t)b.items.size() - b.n0;
+    h.first[0] = 0;
+    h.first[1] = b.n0;
     h.n_problems = (int32_t)b.probs.size();
     h.problems_off = kHeaderBytes;
     h.items_off = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem);
+    for (size_t i = 0; i < b.probs.size(); ++i)
+        b.probs[i].rows = b.rows_off[i] < 0 ? nullptr
+                                            : (uint64_t *)((uint8_t *)table_dev + head +
+                                                           b.rows_off[i]);
     memcpy(host.data(), &h, sizeof h);
     if (!b.probs.empty())
         memcpy(host.data() + h.problems_off, b.probs.data(), b.probs.size() * sizeof(DevProblem));
@@ -381,11 +429,16 @@ int cu_count()
 
 int launch_plan(const BatchPlan &bp, hipStream_t s)
 {
-    if (bp.n_items == 0)
+    if (bp.n_items[0] + bp.n_items[1] == 0)
         return NE_OK;
     k_batch_reset<<<1, 1, 0, s>>>((DevHeader *)bp.table);
-    k_batch<<<bp.grid, kBatchThreads, 0, s>>>((const uint8_t *)bp.table);
-    return launch_status();
+    for (int ph = 0; ph < 2; ++ph)
+        if (bp.n_items[ph] > 0) {
+            k_batch<<<bp.grid[ph], kBatchThreads, 0, s>>>((uint8_t *)bp.table, ph);
+            if (launch_status())
+                return NE_ELAUNCH;
+        }
+    return NE_OK;
 }
 
 } // namespace
@@ -415,8 +468,10 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
         return NE_EINVAL;
     bp->table = table_dev;
     bp->bytes = *table_needed;
-    bp->n_items = (int)b.items.size();
-    bp->grid = std::min<int>(cu_count(), std::max(1, bp->n_items));
+    bp->n_items[0] = b.n0;
+    bp->n_items[1] = (int)b.items.size() - b.n0;
+    for (int ph = 0; ph < 2; ++ph)
+        bp->grid[ph] = std::min<int>(cu_count(), std::max(1, bp->n_items[ph]));
     *plan = (ne_batch_t *)bp;
     return NE_OK;
 }
@@ -430,7 +485,10 @@ int ne_batch_run(const ne_batch_t *plan, ne_stream_t stream)
 
 int ne_batch_items(const ne_batch_t *plan)
 {
-    return plan ? ((const BatchPlan *)plan)->n_items : -1;
+    if (!plan)
+        return -1;
+    const auto *bp = (const BatchPlan *)plan;
+    return bp->n_items[0] + bp->n_items[1];
 }
 
 void ne_batch_free(ne_batch_t *plan) { free(plan); }

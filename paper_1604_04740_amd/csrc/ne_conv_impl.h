@@ -193,11 +193,16 @@ __device__ __forceinline__ void cv_streams(const ConvJob &J, int (&stream)[G])
 // of the block of 1024 outputs starting at t0, every digit pass, folded
 // into red[slot][position] (uint64, mod 2^64).  Ends after a barrier, with
 // red complete.  lds: cv_lds_bytes(G) bytes, 16-byte aligned.
-template <int G, bool FUSED>
+// SPLIT (fused only): the own-stream and previous-stream products of every
+// slot are accumulated in two passes of G accumulator sets each instead of
+// one pass of 2G (half the accumulator registers, twice the staging).
+template <int G, bool FUSED, bool SPLIT = false>
 __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, int Ia, int Ib,
                                                 const int (&stream)[G], int8_t *lds)
 {
-    constexpr int CH = FUSED ? 2 * G : G; // accumulator sets
+    static_assert(FUSED || !SPLIT, "split passes are for the fused form");
+    constexpr int CH = (FUSED && !SPLIT) ? 2 * G : G; // accumulator sets
+    constexpr int HALVES = SPLIT ? 2 : 1;
     int8_t *rings = lds;
     int8_t *gc = lds + G * kCvRing;
     auto *red = (unsigned long long *)(gc + 32 * kCvGStride);
@@ -212,7 +217,9 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
     for (int i = tid; i < G * kCvBlock; i += kCvThreads)
         red[i] = 0;
 
-    for (int d = 0; d < J.digits; ++d) {
+    for (int pass = 0; pass < J.digits * HALVES; ++pass) {
+        const int d = pass / HALVES;
+        const bool prev = SPLIT && (pass & 1); // this pass: previous-stream products
         cv16i acc[CH];
 #pragma unroll
         for (int q = 0; q < CH; ++q)
@@ -262,10 +269,16 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                                                cv_ring_off(i0 + 16 * h - 32 * a));
 #pragma unroll
                     for (int s = 0; s < G; ++s) {
-                        acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[s], 0, 0, 0);
-                        if constexpr (FUSED)
-                            acc[G + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                                A[(s + G - 1) % G], B, acc[G + s], 0, 0, 0);
+                        if constexpr (SPLIT) {
+                            acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                prev ? A[(s + G - 1) % G] : A[s], B, acc[s], 0, 0, 0);
+                        } else {
+                            acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[s], 0, 0,
+                                                                           0);
+                            if constexpr (FUSED)
+                                acc[G + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    A[(s + G - 1) % G], B, acc[G + s], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -284,11 +297,13 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                 const int row = 8 * (e >> 2) + 4 * h + (e & 3);
                 int lo, hi = 0;
                 asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(acc[s][e]));
-                if constexpr (FUSED)
+                if constexpr (FUSED && !SPLIT)
                     asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(acc[G + s][e]));
                 uint64_t v = (uint64_t)(int64_t)lo;
-                if constexpr (FUSED)
+                if constexpr (FUSED && !SPLIT)
                     v += (uint64_t)(int64_t)hi << J.l;
+                if constexpr (SPLIT)
+                    v = prev ? v << J.l : v;
                 atomicAdd(&red[s * kCvBlock + 32 * row + a], v << (8 * d));
             }
         __syncthreads();
@@ -332,14 +347,14 @@ __device__ __forceinline__ void conv_finish(const ConvJob &J, const int (&stream
 
 // One whole block of 1024 outputs (all taps) in one workgroup.  FUSED:
 // G == M, disentangle and check; staged: write delta.
-template <int G, bool FUSED>
+template <int G, bool FUSED, bool SPLIT = false>
 __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
 {
     int stream[G];
     cv_streams<G, FUSED>(J, stream);
     const int64_t t0 = block * kCvBlock;
     const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
-    conv_accumulate<G, FUSED>(J, t0, 0, taps, stream, lds);
+    conv_accumulate<G, FUSED, SPLIT>(J, t0, 0, taps, stream, lds);
     const auto *red = (const unsigned long long *)(lds + G * kCvRing + 32 * kCvGStride);
     const int tid = threadIdx.x;
 #pragma unroll 1

@@ -180,33 +180,50 @@ template <int M> struct PermL {
 };
 
 template <int M> struct PermFusedL {
-    static int run(const void *c, int dt, const int32_t *perm, const int64_t *scale,
-                   const int64_t *add, void *dhat, int out64, uint32_t *flags,
-                   unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
+    template <typename T>
+    static int go(const T *c, uint64_t *rows, const int32_t *perm, const int64_t *scale,
+                  const int64_t *add, void *dhat, int out64, uint32_t *flags,
+                  unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
     {
         const unsigned g = grid_for(N, kThreads);
-        if (dt == NE_I8)
-            k_permute_scale_fused<M, int8_t><<<g, kThreads, 0, s>>>(
-                (const int8_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
-        else if (dt == NE_I32)
-            k_permute_scale_fused<M, int32_t><<<g, kThreads, 0, s>>>(
-                (const int32_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
-        else
-            k_permute_scale_fused<M, int64_t><<<g, kThreads, 0, s>>>(
-                (const int64_t *)c, perm, scale, add, dhat, out64, flags, nb, N, l, r);
+        if (rows) {
+            k_perm_pack<M, T><<<g, kThreads, 0, s>>>(c, rows, N, r);
+            if (launch_status())
+                return NE_ELAUNCH;
+        }
+        k_permute_scale_fused<M, T><<<g, kThreads, 0, s>>>(c, rows, perm, scale, add, dhat, out64,
+                                                          flags, nb, N, l, r);
         return launch_status();
+    }
+    static int run(const void *c, int dt, uint64_t *rows, const int32_t *perm,
+                   const int64_t *scale, const int64_t *add, void *dhat, int out64,
+                   uint32_t *flags, unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
+    {
+        if (dt == NE_I8)
+            return go<int8_t>((const int8_t *)c, rows, perm, scale, add, dhat, out64, flags, nb, N,
+                              l, r, s);
+        if (dt == NE_I32)
+            return go<int32_t>((const int32_t *)c, rows, perm, scale, add, dhat, out64, flags, nb,
+                               N, l, r, s);
+        return go<int64_t>((const int64_t *)c, rows, perm, scale, add, dhat, out64, flags, nb, N,
+                           l, r, s);
     }
 };
 
 } // namespace
 
+int64_t permute_rows_bytes(int64_t N, int M, int c_dtype)
+{
+    return N * ((M * c_dtype + 7) / 8) * 8;
+}
+
 int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
                                const int64_t *scale, const int64_t *add, void *dhat, int out64,
                                uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
-                               int r, hipStream_t s)
+                               int r, void *rows, hipStream_t s)
 {
-    return dispatch_m<PermFusedL>(M, c, c_dtype, perm, scale, add, dhat, out64, flags, n_bad, N,
-                                  l, r, s);
+    return dispatch_m<PermFusedL>(M, c, c_dtype, (uint64_t *)rows, perm, scale, add, dhat, out64,
+                                  flags, n_bad, N, l, r, s);
 }
 
 int launch_entangle(const void *c, int c_dtype, int64_t *eps, int64_t N, int M, int l,

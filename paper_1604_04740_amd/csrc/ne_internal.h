@@ -33,10 +33,13 @@ int launch_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t 
                          const int64_t *add, int64_t *delta, int64_t N, int M, int l,
                          hipStream_t s);
 
+// Bytes of the row copy (M inputs per position, 64-bit padded) that the
+// fused permutation gathers from when given a workspace.
+int64_t permute_rows_bytes(int64_t N, int M, int c_dtype);
 int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
                                const int64_t *scale, const int64_t *add, void *dhat, int out64,
                                uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
-                               int r, hipStream_t s);
+                               int r, void *rows, hipStream_t s);
 
 // ---- matrix-core GEMMs (ne_gemm.hip) ----
 int launch_gemm_plain(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,

@@ -10,20 +10,53 @@ namespace {
 
 constexpr int kPermThreads = 256;
 
+// Row layout of the gather source: the M inputs of one position stored
+// next to each other, in slot order (slot s = stream (r + s) mod M), padded
+// to whole 64-bit words, so that one position's gather is one or two
+// aligned loads instead of M loads from M different cache lines.
+template <int M, typename T>
+struct PermRow {
+    static constexpr int Q = (M * (int)sizeof(T) + 7) / 8; // 64-bit words per row
+};
+
+// Rows of positions [first, last), threads from `first + start`, step
+// `stride`: rows[n][.] = c[(r + s) mod M][n] for every slot s.
+template <int M, typename T>
+__device__ __forceinline__ void perm_pack_range(const T *__restrict__ c,
+                                                uint64_t *__restrict__ rows, int64_t N, int r,
+                                                int64_t first, int64_t last, int64_t start,
+                                                int64_t stride)
+{
+    constexpr int Q = PermRow<M, T>::Q;
+    for (int64_t n = first + start + threadIdx.x; n < last; n += stride) {
+        T v[Q * 8 / sizeof(T)] = {};
+#pragma unroll
+        for (int s = 0; s < M; ++s)
+            v[s] = c[(int64_t)((r + s) % M) * N + n];
+        uint64_t q[Q];
+        __builtin_memcpy(q, v, sizeof q);
+#pragma unroll
+        for (int k = 0; k < Q; ++k)
+            rows[n * Q + k] = q[k];
+    }
+}
+
 // Fused permute / scale / add: for every position n, gather the M input
-// words at perm[n], entangle them (slot s holds stream (r + s) mod M),
-// apply delta = scale * eps + (2^l + 1) add, disentangle and check.  The
+// words at perm[n] (from c, or from its rows when `rows` is given), entangle
+// them (slot s holds stream (r + s) mod M), apply
+// delta = scale * eps + (2^l + 1) add, disentangle and check.  The
 // entangled words exist only in registers.  Wavefronts cover whole flag
 // words (64 consecutive positions).
 // Positions [first, last) (first a multiple of 64), visited by the
 // workgroup's 256 threads starting at `first + start`, step `stride`.
 template <int M, typename T>
 __device__ __forceinline__ void perm_fused_range(
-    const T *__restrict__ c, const int32_t *__restrict__ perm, const int64_t *__restrict__ scale,
-    const int64_t *__restrict__ add, void *__restrict__ dhat, int out64,
-    uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N, int l, int r,
-    int64_t first, int64_t last, int64_t start, int64_t stride)
+    const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
+    int out64, uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N,
+    int l, int r, int64_t first, int64_t last, int64_t start, int64_t stride)
 {
+    constexpr int Q = PermRow<M, T>::Q;
     const int lane = threadIdx.x & 63;
     const int64_t words = (N + 31) / 32;
     unsigned long long count = 0;
@@ -34,9 +67,21 @@ __device__ __forceinline__ void perm_fused_range(
             int64_t src = perm[n];
             src = src < 0 ? 0 : (src >= N ? N - 1 : src);
             int64_t v[M]; // v[s] = input of stream (r + s) mod M, i.e. slot order
+            if (rows) {
+                uint64_t q[Q];
 #pragma unroll
-            for (int s = 0; s < M; ++s)
-                v[s] = (int64_t)c[(int64_t)((r + s) % M) * N + src];
+                for (int k = 0; k < Q; ++k)
+                    q[k] = rows[src * Q + k];
+                T t[Q * 8 / sizeof(T)];
+                __builtin_memcpy(t, q, sizeof q);
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    v[s] = (int64_t)t[s];
+            } else {
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    v[s] = (int64_t)c[(int64_t)((r + s) % M) * N + src];
+            }
             const uint64_t sc = scale ? (uint64_t)scale[n] : 1u;
             const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
             int64_t d[M], o[M];
@@ -68,12 +113,22 @@ __device__ __forceinline__ void perm_fused_range(
 }
 
 template <int M, typename T>
-__global__ __launch_bounds__(kPermThreads) void k_permute_scale_fused(
-    const T *__restrict__ c, const int32_t *__restrict__ perm, const int64_t *__restrict__ scale,
-    const int64_t *__restrict__ add, void *__restrict__ dhat, int out64,
-    uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N, int l, int r)
+__global__ __launch_bounds__(kPermThreads) void k_perm_pack(const T *__restrict__ c,
+                                                            uint64_t *__restrict__ rows,
+                                                            int64_t N, int r)
 {
-    perm_fused_range<M, T>(c, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
+    perm_pack_range<M, T>(c, rows, N, r, 0, N, (int64_t)blockIdx.x * kPermThreads,
+                          (int64_t)gridDim.x * kPermThreads);
+}
+
+template <int M, typename T>
+__global__ __launch_bounds__(kPermThreads) void k_permute_scale_fused(
+    const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
+    const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
+    int out64, uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N,
+    int l, int r)
+{
+    perm_fused_range<M, T>(c, rows, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
                            (int64_t)blockIdx.x * kPermThreads,
                            (int64_t)gridDim.x * kPermThreads);
 }

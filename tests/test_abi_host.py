@@ -120,3 +120,20 @@ def test_conv_workspace_size_and_rejection(ne):
     assert rc == -3  # overlaps d_hat
     rc = L.ne_lsb_circconv(c, 40, g, d, 1000, ctypes.byref(p), ws, need - 8, None)
     assert rc == -1
+
+
+def test_permute_workspace_size_and_rejection(ne):
+    L = ne.lib()
+    assert L.ne_permute_workspace(1000, 3, 1) == 1000 * 8       # 3 int8 inputs -> one word
+    assert L.ne_permute_workspace(1000, 9, 1) == 1000 * 16
+    assert L.ne_permute_workspace(1000, 5, 4) == 1000 * 24      # 20 bytes -> three words
+    assert L.ne_permute_workspace(1000, 3, 8) == 1000 * 24
+    assert L.ne_permute_workspace(0, 3, 1) == 0 and L.ne_permute_workspace(10, 3, 2) == 0
+    p = ne.ne_params_default(3)
+    c, perm, d, ws = (ctypes.c_void_p(a) for a in (1 << 20, 2 << 20, 3 << 20, 4 << 20))
+    rc = L.ne_permute_scale_fused(c, 1, perm, None, None, d, 8, None, None, 1000, ctypes.byref(p),
+                                  ws, 1000 * 8 - 8, None)
+    assert rc == -1
+    rc = L.ne_permute_scale_fused(c, 1, perm, None, None, d, 8, None, None, 1000, ctypes.byref(p),
+                                  c, 1000 * 8, None)
+    assert rc == -3  # overlaps the inputs

@@ -90,6 +90,12 @@ def test_permute_scale_fused(ne, orc, M, N):
     dh, fl, nb = ne.ne_permute_scale_fused(_t(c), _t(perm.astype(np.int32)), None, None, p)
     ref2 = orc.permute_scale_pipeline(c, perm, None, None, r=p.r_check)
     assert np.array_equal(_h(dh), ref2["dhat"])
+    # direct gather from c (no row copy)
+    for cdt in (np.int8, np.int32):
+        dh, fl, nb = ne.ne_permute_scale_fused(_t(c.astype(cdt)), _t(perm.astype(np.int32)),
+                                               _t(s), _t(a), p, workspace=None)
+        ref3 = orc.permute_scale_pipeline(c, perm, s, a, r=p.r_check)
+        assert np.array_equal(_h(dh), ref3["dhat"]) and int(nb.item()) == 0
 
 
 def _problems(ne, recipe):
