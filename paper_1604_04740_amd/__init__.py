@@ -209,7 +209,9 @@ def _conv_ws(workspace, N, M, fused, device):
     if workspace is True:
         need = ne_circconv_workspace(N, M, fused)
         return torch.empty((max(need, 8) // 8,), dtype=torch.int64, device=device) if need else None
-    return workspace or None
+    if workspace is None or workspace is False:
+        return None
+    return workspace
 
 
 def ne_lsb_circconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,

@@ -30,12 +30,14 @@
 //             taps i0 + 16h .. +15 start at v = i0 + 16h - 32a (aligned).
 //             Chunks are XOR-swizzled (bit 0 ^= bit 4) so that the 16 rows
 //             a lane group reads hit 16 different bank groups.
-//   g copies  32 rings of 512 bytes (stride 528 for the banks): copy p
-//             holds B[i][p] at byte i mod 512, so column p's 16 taps are
+//   g copies  32 rings of 1024 bytes (stride 1040 for the banks): copy p
+//             holds B[i][p] at byte i mod 1024, so column p's 16 taps are
 //             one aligned read.
 //   red       [slots][1024] uint64: the folded delta of the block.
-// Each 256-tap step is staged while the previous one is multiplied (the
-// rings slide: 256 new bytes per ring per step); one barrier per step.  The
+// A workgroup with at most four 256-tap steps (a split of the taps) stages
+// all of them at once: one wait for memory, one barrier, then only MFMAs.
+// Longer tap ranges slide: each step is staged while the previous one is
+// multiplied (256 new bytes per ring per step), one barrier per step.  The
 // four wavefronts take two k-steps of each 256-tap step and add their
 // folded partial sums into red with LDS atomics.
 #pragma once
@@ -52,9 +54,10 @@ typedef int cv16i __attribute__((ext_vector_type(16)));
 constexpr int kCvThreads = 256;
 constexpr int kCvBlock = 1024;    // outputs per block
 constexpr int kCvStep = 256;      // taps staged per step
-constexpr int kCvRing = 2048;     // bytes per A ring (>= 992 + 2 * 256)
-constexpr int kCvGRing = 512;     // bytes per g copy (>= 2 * 256)
-constexpr int kCvGStride = 528;   // bytes between g copies
+constexpr int kCvRing = 2048;     // bytes per A ring (>= 992 + 4 * 256)
+constexpr int kCvGRing = 1024;    // bytes per g copy (>= 4 * 256)
+constexpr int kCvGStride = 1040;  // bytes between g copies (16 mod 256: bank spread)
+constexpr int kCvOneShot = 4;     // steps a workgroup stages at once
 constexpr int kCvMaxSlots = 8;
 
 __host__ __device__ constexpr int cv_lds_bytes(int slots)
@@ -227,26 +230,46 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
             for (int e = 0; e < 16; ++e)
                 acc[q][e] = 0;
 
-        // prologue: ring bytes v in [Ia - 992, Ia + 256) and g taps [Ia, Ia + 256)
-        for (int k = tid; k < 992 + kCvStep; k += kCvThreads) {
-            CvA<G> st;
-            const int v = Ia - 992 + k;
-            st.load(J, stream, cv_mod(t0i - v, Ni), v);
-            st.store(rings, d);
+        // prologue: ring bytes v in [Ia - 992, Ia + span) and g taps
+        // [Ia, Ia + span), span = every step (one shot) or the first one;
+        // the loads of a round are all issued before its stores
+        const bool oneshot = steps <= kCvOneShot;
+        const int span = oneshot ? steps * kCvStep : kCvStep;
+        constexpr int RA = G <= 4 ? 4 : 2; // ring bytes in flight per thread and round
+#pragma unroll 1
+        for (int k0 = 0; k0 < 992 + span; k0 += RA * kCvThreads) {
+            CvA<G> st[RA];
+#pragma unroll
+            for (int u = 0; u < RA; ++u) {
+                const int v = Ia - 992 + k0 + u * kCvThreads + tid;
+                if (k0 + u * kCvThreads + tid < 992 + span)
+                    st[u].load(J, stream, cv_mod(t0i - v, Ni), v);
+            }
+#pragma unroll
+            for (int u = 0; u < RA; ++u)
+                if (k0 + u * kCvThreads + tid < 992 + span)
+                    st[u].store(rings, d);
+        }
+#pragma unroll 1
+        for (int u0 = 0; u0 < span; u0 += 2 * kCvStep) {
+            CvG sg[2];
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (u0 + u * kCvStep < span)
+                    sg[u].load(J, Ia + u0 + u * kCvStep, tid);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (u0 + u * kCvStep < span)
+                    sg[u].store(gc);
         }
         // ring coordinate v = Ia + 256 (j + 1) + tid of step j's prefetch,
         // and its input index (t0 - v) mod N, advanced by -256 mod N per step
         int pidx = cv_mod(t0i - Ia - kCvStep - tid, Ni);
-        {
-            CvG sg;
-            sg.load(J, Ia, tid);
-            sg.store(gc);
-        }
         __syncthreads();
 
         for (int j = 0; j < steps; ++j) {
             const int I = Ia + j * kCvStep;
-            const bool more = j + 1 < steps;
+            const bool more = !oneshot && j + 1 < steps;
             CvA<G> na;
             CvG ng;
             if (more) {
@@ -286,8 +309,11 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                 na.store(rings, d);
                 ng.store(gc);
             }
-            __syncthreads();
+            if (!oneshot)
+                __syncthreads();
         }
+        if (oneshot)
+            __syncthreads(); // every wavefront's reads are done before the fold's next pass
 
         // fold this digit's products into red (mod 2^64)
 #pragma unroll
@@ -430,11 +456,21 @@ __global__ __launch_bounds__(256) void k_conv_reduce(const ConvJob J, const uint
         int64_t dd[M];
         const int64_t tc = t < Nb ? t : 0;
 #pragma unroll
-        for (int s = 0; s < M; ++s) {
-            uint64_t v = 0;
-            for (int z = 0; z < S; ++z)
-                v += ws[((int64_t)z * M + s) * Nb + tc];
-            dd[s] = (int64_t)v;
+        for (int s = 0; s < M; ++s)
+            dd[s] = 0;
+        // four splits per round, all loads of a round in flight together
+        for (int z0 = 0; z0 < S; z0 += 4) {
+            uint64_t v[4][M];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    v[u][s] = z0 + u < S ? ws[((int64_t)(z0 + u) * M + s) * Nb + tc] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    dd[s] = (int64_t)((uint64_t)dd[s] + v[u][s]);
         }
         conv_finish<M>(J, stream, t, dd);
     } else {
