@@ -389,7 +389,7 @@ __device__ __forceinline__ void gemm_tile_dma(const typename V::Args &args, int 
     constexpr int LOADS_MIN = REG / 4;             // DMA instructions per tile, fewest over waves
     static_assert(WM * WN == 4, "four wavefronts");
     static_assert(BMS % RPR == 0 && BN % RPR == 0, "regions must not straddle sources");
-    static_assert(S >= 2 && S <= 5, "stages");
+    static_assert(S >= 2 && S <= 8, "stages");
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6); // uniform per wavefront

@@ -57,56 +57,79 @@ __device__ __forceinline__ void perm_fused_range(
     int l, int r, int64_t first, int64_t last, int64_t start, int64_t stride)
 {
     constexpr int Q = PermRow<M, T>::Q;
+    // U groups of 64 positions per wavefront per round: all their gathers
+    // are issued before the first is used (random loads need many in flight)
+    constexpr int U = Q <= 2 ? 4 : 2;
     const int lane = threadIdx.x & 63;
     const int64_t words = (N + 31) / 32;
     unsigned long long count = 0;
-    for (int64_t base = first + start + (threadIdx.x & ~63); base < last; base += stride) {
-        const int64_t n = base + lane;
-        bool f = false;
-        if (n < last) {
-            int64_t src = perm[n];
-            src = src < 0 ? 0 : (src >= N ? N - 1 : src);
-            int64_t v[M]; // v[s] = input of stream (r + s) mod M, i.e. slot order
-            if (rows) {
-                uint64_t q[Q];
+    for (int64_t base0 = first + start + (threadIdx.x & ~63); base0 < last;
+         base0 += U * stride) {
+        int64_t src[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t n = base0 + u * stride + lane;
+            int64_t x = n < last ? perm[n] : 0;
+            src[u] = x < 0 ? 0 : (x >= N ? N - 1 : x);
+        }
+        int64_t v[U][M]; // v[u][s] = input of stream (r + s) mod M, i.e. slot order
+        if (rows) {
+            uint64_t q[U][Q];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int k = 0; k < Q; ++k)
-                    q[k] = rows[src * Q + k];
+                    q[u][k] = rows[src[u] * Q + k];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
                 T t[Q * 8 / sizeof(T)];
-                __builtin_memcpy(t, q, sizeof q);
+                __builtin_memcpy(t, q[u], sizeof q[u]);
 #pragma unroll
                 for (int s = 0; s < M; ++s)
-                    v[s] = (int64_t)t[s];
-            } else {
+                    v[u][s] = (int64_t)t[s];
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
 #pragma unroll
                 for (int s = 0; s < M; ++s)
-                    v[s] = (int64_t)c[(int64_t)((r + s) % M) * N + src];
-            }
-            const uint64_t sc = scale ? (uint64_t)scale[n] : 1u;
-            const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
-            int64_t d[M], o[M];
-#pragma unroll
-            for (int s = 0; s < M; ++s)
-                d[s] = (int64_t)(sc * (uint64_t)entangle_word(v[s], v[(s + M - 1) % M], l) + a);
-            f = disentangle_rot<M>(d, l, o);
-#pragma unroll
-            for (int s = 0; s < M; ++s) {
-                const int64_t idx = (int64_t)((r + s) % M) * N + n;
-                if (out64)
-                    ((int64_t *)dhat)[idx] = o[s];
-                else
-                    ((int32_t *)dhat)[idx] = (int32_t)o[s];
-            }
+                    v[u][s] = (int64_t)c[(int64_t)((r + s) % M) * N + src[u]];
         }
-        const uint64_t mask = __ballot(f);
-        if (flags) {
-            const int64_t w0 = base / 32;
-            if (lane == 0 && w0 < words)
-                flags[w0] = (uint32_t)mask;
-            if (lane == 32 && w0 + 1 < words)
-                flags[w0 + 1] = (uint32_t)(mask >> 32);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t base = base0 + u * stride;
+            if (base >= last)
+                break; // uniform: the same for the whole wavefront
+            const int64_t n = base + lane;
+            bool f = false;
+            if (n < last) {
+                const uint64_t sc = scale ? (uint64_t)scale[n] : 1u;
+                const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
+                int64_t d[M], o[M];
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    d[s] = (int64_t)(sc * (uint64_t)entangle_word(v[u][s], v[u][(s + M - 1) % M], l) +
+                                     a);
+                f = disentangle_rot<M>(d, l, o);
+#pragma unroll
+                for (int s = 0; s < M; ++s) {
+                    const int64_t idx = (int64_t)((r + s) % M) * N + n;
+                    if (out64)
+                        ((int64_t *)dhat)[idx] = o[s];
+                    else
+                        ((int32_t *)dhat)[idx] = (int32_t)o[s];
+                }
+            }
+            const uint64_t mask = __ballot(f);
+            if (flags) {
+                const int64_t w0 = base / 32;
+                if (lane == 0 && w0 < words)
+                    flags[w0] = (uint32_t)mask;
+                if (lane == 32 && w0 + 1 < words)
+                    flags[w0 + 1] = (uint32_t)(mask >> 32);
+            }
+            count += (unsigned long long)__popcll(mask);
         }
-        count += (unsigned long long)__popcll(mask);
     }
     if (n_bad && lane == 0 && count)
         atomicAdd(n_bad, count);
