@@ -60,9 +60,21 @@ constexpr int kCvGStride = 1040;  // bytes between g copies (16 mod 256: bank sp
 constexpr int kCvOneShot = 4;     // steps a workgroup stages at once
 constexpr int kCvMaxSlots = 8;
 
+// A rings allocated for G slots: at least eight, so that a one-shot
+// workgroup can hold every digit of up to eight (slot, digit) sources.
+__host__ __device__ constexpr int cv_rings(int slots)
+{
+    return slots < 8 ? 8 : slots;
+}
+
 __host__ __device__ constexpr int cv_lds_bytes(int slots)
 {
-    return slots * kCvRing + 32 * kCvGStride + slots * kCvBlock * 8;
+    return cv_rings(slots) * kCvRing + 32 * kCvGStride + slots * kCvBlock * 8;
+}
+
+__device__ __forceinline__ unsigned long long *cv_red(int8_t *lds, int slots)
+{
+    return (unsigned long long *)(lds + cv_rings(slots) * kCvRing + 32 * kCvGStride);
 }
 
 // Number of balanced int8 digits for values with |x| < 2^(bits-1).
@@ -134,6 +146,17 @@ struct CvA {
 #pragma unroll
         for (int s = 0; s < G; ++s)
             rings[s * kCvRing + off] = cv_digit(val[s], d);
+    }
+    // every digit: digit dd of slot s into ring s + G dd
+    __device__ __forceinline__ void store_all(int8_t *rings, int digits) const
+    {
+        const int off = cv_ring_off(v);
+#pragma unroll
+        for (int s = 0; s < G; ++s) {
+            int64_t x = val[s];
+            for (int dd = 0; dd < digits; ++dd)
+                rings[(s + G * dd) * kCvRing + off] = digit(x);
+        }
     }
 };
 
@@ -207,8 +230,8 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
     constexpr int CH = (FUSED && !SPLIT) ? 2 * G : G; // accumulator sets
     constexpr int HALVES = SPLIT ? 2 : 1;
     int8_t *rings = lds;
-    int8_t *gc = lds + G * kCvRing;
-    auto *red = (unsigned long long *)(gc + 32 * kCvGStride);
+    int8_t *gc = lds + cv_rings(G) * kCvRing;
+    auto *red = cv_red(lds, G);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -231,35 +254,44 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                 acc[q][e] = 0;
 
         // prologue: ring bytes v in [Ia - 992, Ia + span) and g taps
-        // [Ia, Ia + span), span = every step (one shot) or the first one;
-        // the loads of a round are all issued before its stores
+        // [Ia, Ia + span), span = every step (one shot) or the first one.
+        // One shot: the g copies are staged once, and when every digit's
+        // rings fit, the rings too (later passes only multiply).  Each round
+        // issues all its loads before its stores.
         const bool oneshot = steps <= kCvOneShot;
         const int span = oneshot ? steps * kCvStep : kCvStep;
+        const bool alld = oneshot && G * J.digits <= cv_rings(G);
+        const bool stage_a = !alld || pass == 0;
+        const bool stage_g = !oneshot || pass == 0;
+        const int dsel = alld ? d : 0; // ring group of this pass's digit
         constexpr int RA = G <= 4 ? 4 : 2; // ring bytes in flight per thread and round
+        const int a_bytes = stage_a ? 992 + span : 0, g_steps = stage_g ? span / kCvStep : 0;
 #pragma unroll 1
-        for (int k0 = 0; k0 < 992 + span; k0 += RA * kCvThreads) {
+        for (int r = 0; r * RA * kCvThreads < a_bytes || 2 * r < g_steps; ++r) {
             CvA<G> st[RA];
+            CvG sg[2];
+            const int k0 = r * RA * kCvThreads;
 #pragma unroll
             for (int u = 0; u < RA; ++u) {
                 const int v = Ia - 992 + k0 + u * kCvThreads + tid;
-                if (k0 + u * kCvThreads + tid < 992 + span)
+                if (k0 + u * kCvThreads + tid < a_bytes)
                     st[u].load(J, stream, cv_mod(t0i - v, Ni), v);
             }
 #pragma unroll
+            for (int u = 0; u < 2; ++u)
+                if (2 * r + u < g_steps)
+                    sg[u].load(J, Ia + (2 * r + u) * kCvStep, tid);
+#pragma unroll
             for (int u = 0; u < RA; ++u)
-                if (k0 + u * kCvThreads + tid < 992 + span)
-                    st[u].store(rings, d);
-        }
-#pragma unroll 1
-        for (int u0 = 0; u0 < span; u0 += 2 * kCvStep) {
-            CvG sg[2];
+                if (k0 + u * kCvThreads + tid < a_bytes) {
+                    if (alld)
+                        st[u].store_all(rings, J.digits);
+                    else
+                        st[u].store(rings, d);
+                }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
-                if (u0 + u * kCvStep < span)
-                    sg[u].load(J, Ia + u0 + u * kCvStep, tid);
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-                if (u0 + u * kCvStep < span)
+                if (2 * r + u < g_steps)
                     sg[u].store(gc);
         }
         // ring coordinate v = Ia + 256 (j + 1) + tid of step j's prefetch,
@@ -288,7 +320,7 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                     cv4i A[G];
 #pragma unroll
                     for (int s = 0; s < G; ++s)
-                        A[s] = *(const cv4i *)(rings + s * kCvRing +
+                        A[s] = *(const cv4i *)(rings + (s + G * dsel) * kCvRing +
                                                cv_ring_off(i0 + 16 * h - 32 * a));
 #pragma unroll
                     for (int s = 0; s < G; ++s) {
@@ -381,7 +413,7 @@ __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8
     const int64_t t0 = block * kCvBlock;
     const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
     conv_accumulate<G, FUSED, SPLIT>(J, t0, 0, taps, stream, lds);
-    const auto *red = (const unsigned long long *)(lds + G * kCvRing + 32 * kCvGStride);
+    const auto *red = cv_red(lds, G);
     const int tid = threadIdx.x;
 #pragma unroll 1
     for (int q = 0; q < kCvBlock / kCvThreads; ++q) {
@@ -433,7 +465,7 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_part(ConvJob J, uint64_t *w
     const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
     const int z = blockIdx.y, Ia = z * KC, Ib = Ia + KC < taps ? Ia + KC : taps;
     conv_accumulate<G, FUSED>(J, t0, Ia, Ib, stream, lds);
-    const auto *red = (const unsigned long long *)(lds + G * kCvRing + 32 * kCvGStride);
+    const auto *red = cv_red(lds, G);
     const int64_t Nb = (int64_t)gridDim.x * kCvBlock;
     for (int i = threadIdx.x; i < G * kCvBlock; i += kCvThreads) {
         const int s = i / kCvBlock, pos = i % kCvBlock;
