@@ -159,6 +159,15 @@ def run_gemm(args, ne, ne_synth, np, torch, dev):
     assert torch.equal(C.reshape(M, n, N), out), "fused d_hat differs from the plain GEMM"
     del C
 
+    # the same matrix-core work without entanglement: both int8 products of
+    # every stream (c_m and c_{m-1} times G) as one plain GEMM of 2 M n rows
+    log("limb GEMM (2 M n rows, no entangle / disentangle / check)")
+    A2 = torch.cat([c_d, torch.roll(c_d, 1, dims=0)], dim=0).reshape(2 * M * n, K).contiguous()
+    C2 = torch.empty((2 * M * n, N), dtype=torch.int32, device=dev)
+    t_limb = time_launches(lambda: ne.ne_plain_gemm_i8(A2, Gt_d, out=C2), args.steps, args.warmup,
+                           torch)
+    del A2, C2
+
     log("checksum ABFT GEMM")
     d_abft = torch.empty((M, n, N), dtype=torch.int32, device=dev)
     nb2 = torch.zeros((1,), dtype=torch.int64, device=dev)
@@ -223,6 +232,8 @@ def run_gemm(args, ne, ne_synth, np, torch, dev):
         "issued_tops_entangled": achieved,
         "plain_ms": t_plain, "plain_tops": useful_ops / (t_plain * 1e-3) / 1e12,
         "overhead_vs_plain_pct": 100.0 * (t_fused / t_plain - 1.0),
+        "limb_ms": t_limb,
+        "overhead_ne_pct": 100.0 * (t_fused / t_limb - 1.0),
         "abft_ms": t_abft, "abft_useful_tops": useful_ops / (t_abft * 1e-3) / 1e12,
         "abft_issued_tops": 2.0 * (M + 2) * n * K * N / (t_abft * 1e-3) / 1e12,
         "abft_overhead_vs_plain_pct": 100.0 * (t_abft / t_plain - 1.0),

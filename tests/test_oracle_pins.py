@@ -361,3 +361,45 @@ def test_empty_streams(orc):
     d = np.zeros((3, 0), dtype=np.int64)
     dhat, flags, bad = orc.extract_check(d, 64, 22, 0)
     assert dhat.shape == (3, 0) and bad == 0
+
+
+@pytest.mark.parametrize("M", [3, 5, 8])
+def test_lsb_homomorphism(orc, M):
+    """Section III-A: an LSB operation on the entangled streams gives the
+    entangled outputs, delta_i = d_i + 2^l d_{i-1} (mod 2^64), where d is the
+    plain operation on the plain inputs.  d comes from numpy / Python
+    integers; delta from the oracle's entangle followed by its operation on
+    words.  GEMM, circular convolution and permute + scale + add."""
+    l, k = orc.params(M, 64)
+    rng = np.random.default_rng(1700 + M)
+
+    def ent(d):
+        out = np.empty_like(d)
+        for i in range(M):
+            for idx in np.ndindex(d.shape[1:]):
+                out[(i,) + idx] = _wrap(int(d[(i,) + idx]) + (int(d[((i - 1) % M,) + idx]) << l), 64)
+        return out
+
+    # GEMM, 7 x 9 times 9 x 5
+    c = rng.integers(-128, 128, (M, 7, 9))
+    G = rng.integers(-128, 128, (9, 5))
+    d = np.stack([c[i] @ G for i in range(M)])
+    delta = np.stack([orc.gemm(e, G) for e in orc.entangle(c, 64, l)])
+    assert np.array_equal(delta, ent(d))
+    # circular convolution, N = 11
+    x = rng.integers(-1000, 1000, (M, 11))
+    g = rng.integers(-64, 64, 11)
+    d = np.stack([[sum(int(x[i][(t - j) % 11]) * int(g[j]) for j in range(11)) for t in range(11)]
+                  for i in range(M)])
+    delta = np.stack([orc.circconv(e, g) for e in orc.entangle(x, 64, l)])
+    assert np.array_equal(delta, ent(d))
+    # permutation, scaling, addition (the constant enters self-entangled)
+    n = 13
+    x = rng.integers(-1000, 1000, (M, n))
+    perm = rng.permutation(n)
+    s = rng.integers(-50, 50, n)
+    a = rng.integers(-50, 50, n)
+    d = np.stack([s * x[i][perm] + a for i in range(M)])
+    a_ent = orc.self_entangle(a, 64, l)
+    delta = np.stack([orc.permute_scale(e, perm, s, a_ent) for e in orc.entangle(x, 64, l)])
+    assert np.array_equal(delta, ent(d))
