@@ -362,23 +362,29 @@ typedef struct ne_batch ne_batch_t; /* opaque host-side plan */
 
 /*
  * Plan a batch: validates every problem, splits it into work items (GEMM
- * output tiles, 256-position convolution blocks, permute/scale chunks),
- * orders them longest-first and writes problem table + items into the
- * caller's device buffer table_dev (256-byte aligned, table_bytes long; it
- * must not be in use by a pending run).  With table_dev == NULL only
- * *table_needed is set.  tuning may be NULL (defaults).  On success *plan is
- * a small host object (the only thing the library allocates; free it with
- * ne_batch_free).  Setup call: blocking, not for graph capture.
+ * output tiles, 1024-position convolution blocks, permute/scale chunks: a
+ * copy of the inputs into rows, then the gather), deals them to one list
+ * per XCD (a GEMM's tiles in eight runs of neighbouring tiles, so that the
+ * tiles sharing an L2 share operands; the other items in turn), orders each
+ * list longest-first, and writes the problem table, the lists and room for
+ * the row copies into the caller's device buffer table_dev (256-byte
+ * aligned, table_bytes long; it must not be in use by a pending run).  With
+ * table_dev == NULL only *table_needed is set.  tuning may be NULL
+ * (defaults).  On success *plan is a small host object (the only thing the
+ * library allocates; free it with ne_batch_free).  Setup call: blocking,
+ * not for graph capture.
  */
 int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tuning_t *tuning,
                   void *table_dev, int64_t table_bytes, int64_t *table_needed,
                   ne_batch_t **plan);
 
 /*
- * Run a planned batch: one persistent launch (one workgroup per compute
- * unit) preceded by a one-thread counter reset.  Both are kernels, so the
- * call can be captured into a HIP graph and replayed.  Runs on one stream
- * must not overlap (they share the table's work counter).
+ * Run a planned batch: two persistent launches (one workgroup per compute
+ * unit): GEMM tiles, convolution blocks and row copies, then the
+ * permutation gathers.  The workgroups of an XCD take its list's items in
+ * turn.  Plain kernels only, so the call can be captured into a HIP graph
+ * and replayed.  Runs that share a table must not overlap (the row copies
+ * live in the table).
  */
 int ne_batch_run(const ne_batch_t *plan, ne_stream_t stream);
 

@@ -11,13 +11,15 @@
 // tile choices of every (operation, M, size-class) bucket on the device and
 // returns the fastest per bucket.
 //
-// Device side: ne_batch_run launches a counter reset and the persistent
-// kernel twice (grid = one workgroup per CU): phase 0 runs every GEMM tile,
-// convolution block and row copy, phase 1 the permutation gathers that read
-// those rows.  Every workgroup takes the next item of its phase from a
-// global atomic counter; it exits when the counter passes the item count,
-// so the grid always drains.  All launches are plain kernels (no memset
-// nodes), so ne_batch_run can be captured in a HIP graph and replayed.
+// Device side: ne_batch_run launches the persistent kernel twice (grid =
+// one workgroup per CU): phase 0 runs every GEMM tile, convolution block and
+// row copy, phase 1 the permutation gathers that read those rows.  Items
+// are dealt to eight lists, one per XCD (a GEMM's tiles in eight runs of
+// neighbouring tiles, the other items in turn), each longest-first; the
+// workgroups of an XCD take its list's items in turn.  Every loop is
+// bounded by the item counts in the table, so the grid always drains.  Both
+// launches are plain kernels (no memset nodes), so ne_batch_run can be
+// captured in a HIP graph and replayed.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -56,15 +58,58 @@ struct DevItem {
 };
 
 // Two phases, one launch each: the second (permutation gathers) reads the
-// row copies the first wrote.  Phase p's items are items[first[p] ..).
+// row copies the first wrote.  Each phase keeps one item list per XCD:
+// list x of phase p is items[first[p][x] .. first[p][x] + count[p][x]).
+constexpr int kXcds = 8;
 struct DevHeader {
-    unsigned int counter[2];
-    int32_t n_items[2], first[2];
+    int32_t first[2][kXcds], count[2][kXcds];
     int32_t n_problems, pad;
     int64_t problems_off, items_off;
 };
 
 constexpr int64_t kHeaderBytes = 256;
+
+// The item and problem records are the same in every lane; passing every
+// field through readfirstlane states it, which keeps the buffer descriptors
+// built from them in SGPRs (no per-load waterfall loops).
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni(int64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T *uni(T *p)
+{
+    return (T *)(uintptr_t)uni((int64_t)(uintptr_t)p);
+}
+
+__device__ __forceinline__ DevProblem uniform(const DevProblem &x)
+{
+    DevProblem u;
+    u.op = uni(x.op);
+    u.M = uni(x.M);
+    u.l = uni(x.l);
+    u.r = uni(x.r);
+    u.out64 = uni(x.out64);
+    u.bn = uni(x.bn);
+    u.tiles_m = uni(x.tiles_m);
+    u.tiles_n = uni(x.tiles_n);
+    u.n = uni(x.n);
+    u.K = uni(x.K);
+    u.N = uni(x.N);
+    u.chunk = uni(x.chunk);
+    u.c = uni(x.c);
+    u.g = uni(x.g);
+    u.perm = uni(x.perm);
+    u.scale = uni(x.scale);
+    u.add = uni(x.add);
+    u.dhat = uni(x.dhat);
+    u.flags = uni(x.flags);
+    u.n_bad = uni(x.n_bad);
+    u.rows = uni(x.rows);
+    return u;
+}
 
 template <int M, int BN>
 __device__ __forceinline__ void run_gemm_tile(const DevProblem &P, int tm, int tn, int8_t *lds)
@@ -173,31 +218,24 @@ constexpr int kBatchLds = 3 * 49152; // largest GEMM ring (M = 4, BN = 256 / M =
 static_assert(dma_lds_bytes<FusedV<4, 256>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
 static_assert(dma_lds_bytes<FusedV<8, 128>, kGemmBK, kGemmStages>() <= kBatchLds, "LDS");
 static_assert(cv_lds_bytes(kCvMaxSlots) <= kBatchLds, "LDS");
+static_assert(sizeof(DevHeader) <= kHeaderBytes, "header");
 
-__global__ void k_batch_reset(DevHeader *h)
-{
-    h->counter[0] = 0u;
-    h->counter[1] = 0u;
-}
-
-__global__ __launch_bounds__(kBatchThreads, 1) void k_batch(uint8_t *table, int phase)
+// Workgroup w runs on XCD w mod 8 (workgroups are placed on the XCDs in
+// turn) and takes every (gridDim / 8)-th item of that XCD's list, starting
+// at w / 8: the tiles that share an XCD's L2 are neighbours in their
+// problem, and no item is fetched through a global counter.
+__global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table, int phase)
 {
     __shared__ __attribute__((aligned(1024))) int8_t lds[kBatchLds];
-    __shared__ int item_sh;
-    auto *h = (DevHeader *)table;
+    const auto *h = (const DevHeader *)table;
     const auto *problems = (const DevProblem *)(table + h->problems_off);
-    const auto *items = (const DevItem *)(table + h->items_off) + h->first[phase];
-    const int n_items = h->n_items[phase];
-    for (;;) {
-        if (threadIdx.x == 0)
-            item_sh = (int)atomicAdd(&h->counter[phase], 1u);
-        __syncthreads();
-        const int it = item_sh;
-        __syncthreads();
-        if (it >= n_items)
-            break;
-        const DevItem im = items[it];
-        const DevProblem &P = problems[im.problem];
+    const auto *items = (const DevItem *)(table + h->items_off);
+    const int x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
+    const int first = uni(h->first[phase][x]), count = uni(h->count[phase][x]);
+    for (int i = blockIdx.x / kXcds; i < count; i += per) {
+        const DevItem im0 = items[first + i];
+        const DevItem im = {uni(im0.problem), uni(im0.a), uni(im0.b), uni(im0.kind)};
+        const DevProblem P = uniform(problems[im.problem]);
         if (P.op == NE_OP_GEMM)
             run_gemm(P, im.a, im.b, lds);
         else if (P.op == NE_OP_CONV)
@@ -228,7 +266,7 @@ struct BatchPlan {
     void *table;
     int64_t bytes;
     int n_items[2];
-    int grid[2];
+    int grid; // a multiple of 8: every XCD gets the same number of workgroups
 };
 
 } // namespace ne
@@ -291,8 +329,9 @@ double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
 
 struct Built {
     std::vector<DevProblem> probs;
-    std::vector<DevItem> items; // phase 0 items, then phase 1 items
-    int n0 = 0;
+    std::vector<DevItem> items; // by phase, then by XCD
+    int first[2][kXcds] = {}, count[2][kXcds] = {};
+    int n_phase[2] = {};
     std::vector<int64_t> rows_off; // per problem, offset of its row copy (or -1)
     int64_t rows_bytes = 0;
 };
@@ -302,8 +341,10 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
     struct Tmp {
         DevItem it;
         double cost;
+        int xcd;
     };
-    std::vector<Tmp> tmp, tmp2; // phase 0, phase 1
+    std::vector<Tmp> tmp[2]; // phase 0, phase 1
+    int rr = 0;              // XCD of the next item without locality
     out.probs.resize(count);
     out.rows_off.assign(count, -1);
     out.rows_bytes = 0;
@@ -342,14 +383,22 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
             d.tiles_m = (int)((q.n + 31) / 32);
             d.tiles_n = (int)((q.N + bn - 1) / bn);
             const double c1 = item_cost(q, bn, 0);
-            for (int tn = 0; tn < d.tiles_n; ++tn)
-                for (int tm = 0; tm < d.tiles_m; ++tm)
-                    tmp.push_back({{i, tm, tn, 0}, c1});
+            // groups of 8 row tiles by every column tile (row tile fastest),
+            // cut into one contiguous run per XCD: each L2 holds a compact
+            // block of the problem's rows and columns
+            const int64_t ntiles = (int64_t)d.tiles_m * d.tiles_n;
+            int64_t j = 0;
+            for (int g0 = 0; g0 < d.tiles_m; g0 += 8) {
+                const int gm = std::min(8, d.tiles_m - g0);
+                for (int tn = 0; tn < d.tiles_n; ++tn)
+                    for (int tm = g0; tm < g0 + gm; ++tm, ++j)
+                        tmp[0].push_back({{i, tm, tn, 0}, c1, (int)(j * kXcds / ntiles)});
+            }
         } else if (q.op == NE_OP_CONV) {
             const int blocks = (int)((q.N + kCvBlock - 1) / kCvBlock);
             const double c1 = item_cost(q, 0, 0);
             for (int b = 0; b < blocks; ++b)
-                tmp.push_back({{i, b, 0, 0}, c1});
+                tmp[0].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
         } else {
             int64_t chunk = tuning ? tuning->perm_chunk[q.M - 3][cls] : 16384;
             if (chunk < 64)
@@ -361,20 +410,27 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
             out.rows_off[i] = out.rows_bytes;
             out.rows_bytes += (permute_rows_bytes(q.N, q.M, NE_I8) + 255) / 256 * 256;
             for (int b = 0; b < chunks; ++b) {
-                tmp.push_back({{i, b, 0, 1}, c1 / 4}); // row copy: streaming
-                tmp2.push_back({{i, b, 0, 0}, c1});
+                tmp[0].push_back({{i, b, 0, 1}, c1 / 4, rr % kXcds}); // row copy: streaming
+                tmp[1].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
             }
         }
     }
-    auto by_cost = [](const Tmp &a, const Tmp &b) { return a.cost > b.cost; };
-    std::stable_sort(tmp.begin(), tmp.end(), by_cost);
-    std::stable_sort(tmp2.begin(), tmp2.end(), by_cost);
-    out.n0 = (int)tmp.size();
-    out.items.resize(tmp.size() + tmp2.size());
-    for (size_t i = 0; i < tmp.size(); ++i)
-        out.items[i] = tmp[i].it;
-    for (size_t i = 0; i < tmp2.size(); ++i)
-        out.items[tmp.size() + i] = tmp2[i].it;
+    // every XCD list longest-first (stable: a problem's run keeps its order)
+    auto by_xcd_cost = [](const Tmp &a, const Tmp &b) {
+        return a.xcd != b.xcd ? a.xcd < b.xcd : a.cost > b.cost;
+    };
+    out.items.clear();
+    for (int ph = 0; ph < 2; ++ph) {
+        std::stable_sort(tmp[ph].begin(), tmp[ph].end(), by_xcd_cost);
+        out.n_phase[ph] = (int)tmp[ph].size();
+        for (int x = 0; x < kXcds; ++x) {
+            out.first[ph][x] = (int)out.items.size();
+            for (const Tmp &t : tmp[ph])
+                if (t.xcd == x)
+                    out.items.push_back(t.it);
+            out.count[ph][x] = (int)out.items.size() - out.first[ph][x];
+        }
+    }
     return NE_OK;
 }
 
@@ -396,10 +452,11 @@ int upload(Built &b, void *table_dev)
     const int64_t head = table_head_bytes(b);
     std::vector<uint8_t> host(head, 0);
     DevHeader h{};
-    h.n_items[0] = b.n0;
-    h.n_items[1] = (int32_t)b.items.size() - b.n0;
-    h.first[0] = 0;
-    h.first[1] = b.n0;
+    for (int ph = 0; ph < 2; ++ph)
+        for (int x = 0; x < kXcds; ++x) {
+            h.first[ph][x] = b.first[ph][x];
+            h.count[ph][x] = b.count[ph][x];
+        }
     h.n_problems = (int32_t)b.probs.size();
     h.problems_off = kHeaderBytes;
     h.items_off = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem);
@@ -431,10 +488,9 @@ int launch_plan(const BatchPlan &bp, hipStream_t s)
 {
     if (bp.n_items[0] + bp.n_items[1] == 0)
         return NE_OK;
-    k_batch_reset<<<1, 1, 0, s>>>((DevHeader *)bp.table);
     for (int ph = 0; ph < 2; ++ph)
         if (bp.n_items[ph] > 0) {
-            k_batch<<<bp.grid[ph], kBatchThreads, 0, s>>>((uint8_t *)bp.table, ph);
+            k_batch<<<bp.grid, kBatchThreads, 0, s>>>((const uint8_t *)bp.table, ph);
             if (launch_status())
                 return NE_ELAUNCH;
         }
@@ -468,10 +524,9 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
         return NE_EINVAL;
     bp->table = table_dev;
     bp->bytes = *table_needed;
-    bp->n_items[0] = b.n0;
-    bp->n_items[1] = (int)b.items.size() - b.n0;
-    for (int ph = 0; ph < 2; ++ph)
-        bp->grid[ph] = std::min<int>(cu_count(), std::max(1, bp->n_items[ph]));
+    bp->n_items[0] = b.n_phase[0];
+    bp->n_items[1] = b.n_phase[1];
+    bp->grid = std::max(kXcds, cu_count() / kXcds * kXcds);
     *plan = (ne_batch_t *)bp;
     return NE_OK;
 }
