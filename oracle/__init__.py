@@ -15,6 +15,9 @@ Parity status of each function (what pins it is listed in tests/):
   gemm, circconv, permute_scale pinned (numpy / Python-int textbook results)
   extract, check, extract3      pinned (exhaustive tiny w, closed forms)
   abft_checksum, abft_check     pinned (sum identities, recovery)
+  series_bound, series_pipeline pinned (plain series in Python integers,
+                                homomorphism after every step, extremal
+                                inputs at the bound, tiny-w range edge)
 """
 from __future__ import annotations
 
@@ -279,3 +282,76 @@ def permute_scale_pipeline(c, perm, scale, add, w: int = 64, r: int = 0):
     delta = np.stack([permute_scale(eps[m], perm, scale, add_ent, w) for m in range(M)])
     dhat, flags, bad = extract_check(delta, w, l, r)
     return dict(eps=eps, delta=delta, dhat=dhat, flags=flags, n_bad=bad, l=l, k=k)
+
+
+# ------------------------------------------------------- operation series
+
+def series_bound(c_max: int, ops) -> int:
+    """A-priori bound on |output| after a series of LSB operations applied
+    in turn to inputs with |c| <= c_max (section II: operators applied
+    consecutively; the output range condition of section III-C then holds
+    for the series' final output).  Exact Python integers.  ops are tuples
+      ('gemm', K, g_max)     contraction of length K with |G| <= g_max
+      ('conv', N, g_max)     circular convolution over N taps, |g| <= g_max
+      ('scale_add', s_max, a_max)   s * x + a with |s| <= s_max, |a| <= a_max
+      ('permute',)           bijective index map
+    """
+    B = int(c_max)
+    for op in ops:
+        kind = op[0]
+        if kind in ("gemm", "conv"):
+            B = B * int(op[1]) * int(op[2])
+        elif kind == "scale_add":
+            B = B * int(op[1]) + int(op[2])
+        elif kind == "permute":
+            pass
+        else:
+            raise ValueError(kind)
+    return B
+
+
+def _series_step(x, op, w: int, l: int):
+    """One LSB operation applied to every stream of x [M][...] (words mod 2^w).
+    The + constant is entangled with itself first (footnote of section III-A)."""
+    M = x.shape[0]
+    kind = op[0]
+    if kind == "gemm":
+        G = _a64(op[1])
+        K = G.shape[0]
+        y = gemm(x.reshape(-1, K), G, w)
+        return y.reshape(M, -1, G.shape[1])
+    flat = x.reshape(M, -1)
+    if kind == "conv":
+        return np.stack([circconv(flat[m], op[1], w) for m in range(M)])
+    if kind == "scale_add":
+        scale, add = op[1], op[2]
+        n = flat.shape[1]
+        ident = np.arange(n, dtype=np.int64)
+        a = self_entangle(add, w, l) if add is not None else None
+        return np.stack([permute_scale(flat[m], ident, scale, a, w) for m in range(M)])
+    if kind == "permute":
+        return np.stack([permute_scale(flat[m], op[1], None, None, w) for m in range(M)])
+    raise ValueError(kind)
+
+
+def series_pipeline(c, ops, w: int = 64, r: int = 0, l: int | None = None):
+    """Entangle the M input streams once, apply a series of LSB operations to
+    the entangled streams (section II), then disentangle and check once
+    (section III-C).  c is [M][...]; ops are
+      ('gemm', G)            each stream viewed as rows of G.shape[0] entries
+      ('conv', g)            circular convolution of the flattened stream
+      ('scale_add', s, a)    y[q] = s[q] x[q] + a[q] (either may be None)
+      ('permute', perm)      y[q] = x[perm[q]]
+    Returns dict with eps, delta (after the last operation), dhat, flags,
+    n_bad, (l, k)."""
+    c = _a64(c)
+    M = c.shape[0]
+    lk = params(M, w)
+    l = lk[0] if l is None else l
+    eps = entangle(c, w, l)
+    x = eps
+    for op in ops:
+        x = _series_step(x, op, w, l)
+    delta = x
+    dhat, flags, bad = extract_check(delta, w, l, r)
+    return dict(eps=eps, delta=delta, dhat=dhat, flags=flags, n_bad=bad, l=l, k=lk[1])

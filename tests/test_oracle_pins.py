@@ -403,3 +403,116 @@ def test_lsb_homomorphism(orc, M):
     a_ent = orc.self_entangle(a, 64, l)
     delta = np.stack([orc.permute_scale(e, perm, s, a_ent) for e in orc.entangle(x, 64, l)])
     assert np.array_equal(delta, ent(d))
+
+
+# ------------------------------------------------------------------ series
+
+def _plain_series(c, ops, M):
+    """The series applied to each plain stream with Python integers: numpy
+    object arrays for the products, explicit sums for the convolution,
+    fancy indexing for the permutation."""
+    out = []
+    for m in range(M):
+        x = np.array(c[m], dtype=object)
+        for op in ops:
+            kind = op[0]
+            if kind == "gemm":
+                G = np.array(op[1], dtype=object)
+                x = x.reshape(-1, G.shape[0]).dot(G)
+            elif kind == "conv":
+                x = x.reshape(-1)
+                N = x.size
+                g = [int(v) for v in op[1]]
+                x = np.array([sum(x[(t - j) % N] * g[j] for j in range(N)) for t in range(N)],
+                             dtype=object)
+            elif kind == "scale_add":
+                x = x.reshape(-1)
+                s = np.array(op[1], dtype=object) if op[1] is not None else 1
+                a = np.array(op[2], dtype=object) if op[2] is not None else 0
+                x = s * x + a
+            elif kind == "permute":
+                x = x.reshape(-1)[np.asarray(op[1])]
+        out.append(x.reshape(-1))
+    return out
+
+
+@pytest.mark.parametrize("M", [3, 4, 8])
+def test_series_matches_plain_series(orc, M):
+    """Section II: a series of LSB operations on the entangled streams,
+    disentangled once at the end, returns the series applied to each plain
+    stream, exactly, with no flags; the final entangled words are E(d)."""
+    l, k = orc.params(M, 64)
+    rng = np.random.default_rng(2200 + M)
+    n, K, N = 6, 10, 7
+    c = rng.integers(-128, 128, (M, n, K))
+    G = rng.integers(-128, 128, (K, N))
+    q = n * N
+    s1 = rng.integers(-100, 100, q)
+    a1 = rng.integers(-1000, 1000, q)
+    p1 = rng.permutation(q)
+    g2 = rng.integers(-64, 64, q)
+    p2 = rng.permutation(q)
+    G3 = rng.integers(-20, 20, (N, 3))
+    series = [
+        [("gemm", G), ("scale_add", s1, a1), ("permute", p1)],
+        [("gemm", G), ("permute", p1), ("conv", g2), ("scale_add", None, a1)],
+        [("gemm", G), ("scale_add", s1, None), ("permute", p2), ("gemm", G3)],
+    ]
+    for ops in series:
+        res = orc.series_pipeline(c, ops)
+        want = _plain_series(c, ops, M)
+        assert res["n_bad"] == 0 and not res["flags"].any()
+        for m in range(M):
+            assert [int(v) for v in res["dhat"][m].reshape(-1)] == [int(v) for v in want[m]]
+            ent = [_wrap(int(want[m][i]) + (int(want[(m - 1) % M][i]) << l), 64)
+                   for i in range(want[m].size)]
+            assert [int(v) for v in res["delta"][m].reshape(-1)] == ent
+
+
+def test_series_bound_is_attained(orc):
+    """The composed a-priori bound equals the output for the extremal input
+    (every operand at its bound, same sign), and random inputs stay within
+    it: the bound of a GEMM of length K is K c_max g_max, of a scale/add
+    s_max B + a_max, a permutation leaves it unchanged."""
+    M = 3
+    rng = np.random.default_rng(2301)
+    n, K, N = 4, 9, 5
+    c_max, g_max, s_max, a_max = 120, 110, 7, 900
+    q = n * N
+    ops_b = [("gemm", K, g_max), ("scale_add", s_max, a_max), ("permute",), ("conv", q, 3)]
+    B = orc.series_bound(c_max, ops_b)
+    assert B == ((c_max * K * g_max) * s_max + a_max) * q * 3
+    c = np.full((M, n, K), c_max)
+    ops = [("gemm", np.full((K, N), g_max)), ("scale_add", np.full(q, s_max), np.full(q, a_max)),
+           ("permute", rng.permutation(q)), ("conv", np.full(q, 3))]
+    out = _plain_series(c, ops, M)
+    assert all(int(v) == B for m in range(M) for v in out[m])
+    for _ in range(3):
+        c = rng.integers(-c_max, c_max + 1, (M, n, K))
+        ops = [("gemm", rng.integers(-g_max, g_max + 1, (K, N))),
+               ("scale_add", rng.integers(-s_max, s_max + 1, q), rng.integers(-a_max, a_max + 1, q)),
+               ("permute", rng.permutation(q)), ("conv", rng.integers(-3, 4, q))]
+        out = _plain_series(c, ops, M)
+        assert max(abs(int(v)) for m in range(M) for v in out[m]) <= B
+
+
+def test_series_intermediate_wrap_tiny_w(orc):
+    """Only the series' final output must lie in [-D, D]: at w = 16 an
+    intermediate far outside the range (the entangled words wrap mod 2^16)
+    still disentangles exactly once a later operation brings it back, since
+    every operation is linear mod 2^w.  A final output outside the range
+    does not."""
+    M, w = 3, 16
+    l, k = orc.params(M, w)
+    D = orc.range_bound(M, l, k)
+    rng = np.random.default_rng(2302)
+    n = 40
+    c = rng.integers(-D, D + 1, (M, n))
+    big = np.full(n, 50 * D)
+    perm = rng.permutation(n)
+    ops = [("scale_add", None, big), ("permute", perm), ("scale_add", None, -big)]
+    res = orc.series_pipeline(c, ops, w=w)
+    assert res["n_bad"] == 0
+    assert np.array_equal(res["dhat"], c[:, perm])
+    res = orc.series_pipeline(c, ops[:2], w=w)
+    assert not np.array_equal(res["dhat"], c[:, perm] + 50 * D)
