@@ -291,6 +291,89 @@ def run_conv(args, ne, ne_synth, np, torch, dev):
     return line
 
 
+def run_series(args, ne, ne_synth, np, torch, dev):
+    """Operation series GEMM -> scale/add -> permutation on the entangled
+    streams with one disentangle + check (the fused two-launch entry point),
+    M = 4, 4096^3, scale U[-100,100), add U[-1000,1000), a random permutation
+    of the 4096 x 4096 output positions."""
+    import oracle
+
+    seed = ne_synth.BASE_SEED + 5
+    c, G, c_d, Gt_d = gemm_inputs(ne_synth, np, torch, dev, seed)
+    q = n * N
+    s = ne_synth.uniform_int(seed, 11, (q,), -100, 100)
+    a = ne_synth.uniform_int(seed, 12, (q,), -1000, 1000)
+    log("permutation of the output positions")
+    perm = ne_synth.permutation(seed, 13, q)
+    p = ne.ne_params_default(M)
+    s_d, a_d = torch.from_numpy(s).to(dev), torch.from_numpy(a).to(dev)
+    perm_d = torch.from_numpy(perm.astype(np.int32)).to(dev)
+    out = torch.empty((M, q), dtype=torch.int32, device=dev)
+    fl = torch.empty(((q + 31) // 32,), dtype=torch.int32, device=dev)
+    nb = torch.zeros((1,), dtype=torch.int64, device=dev)
+    ws = torch.empty((ne.ne_series_workspace(n, N, M) // 8,), dtype=torch.int64, device=dev)
+
+    def step():
+        ne.ne_series_gemm_scale_permute(c_d, Gt_d, s_d, a_d, perm_d, p, scale_max=100,
+                                        add_max=1000, out=out, flags=fl, n_bad=nb, workspace=ws)
+
+    log("fused series GEMM -> scale/add -> permutation -> disentangle + check")
+    t = time_launches(step, args.steps, args.warmup, torch)
+    assert int(nb.item()) == 0, "clean run flagged positions"
+    log("sampled parity against the oracle")
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for qq in rng.integers(0, q, 4):
+        row, col = divmod(int(perm[qq]), N)
+        ref = oracle.gemm_pipeline(c[:, row:row + 1, :], G)["dhat"][:, 0, col]
+        want = s[perm[qq]] * ref + a[perm[qq]]
+        assert np.array_equal(got[:, qq].astype(np.int64), want), "series differs from oracle"
+    del got
+    log("fused GEMM alone (entangle + GEMM + disentangle + check)")
+    dh = torch.empty((M, n, N), dtype=torch.int32, device=dev)
+    fl2 = torch.empty((n, (N + 31) // 32), dtype=torch.int32, device=dev)
+    t_gemm = time_launches(lambda: ne.ne_gemm_fused(c_d, Gt_d, p, out=dh, flags=fl2, n_bad=nb),
+                           args.steps, args.warmup, torch)
+    del dh, fl2
+    useful = 2.0 * M * n * K * N
+    issued = 2.0 * 2 * M * n * K * N
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        rows = 64
+        while True:
+            sub_q = rows * N
+            sub_perm = ne_synth.permutation(seed, 14, sub_q)
+            t0 = time.perf_counter()
+            ref = oracle.series_pipeline(c[:, :rows, :], [("gemm", G), ("scale_add", s[:sub_q],
+                                                                        a[:sub_q]),
+                                                           ("permute", sub_perm)])
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or rows >= n:
+                break
+            rows = min(n, max(rows * 2, int(rows * args.cpu_seconds / max(dt, 1e-3) * 1.1)))
+        assert ref["n_bad"] == 0
+        cpu = {"value": 2.0 * M * rows * K * N / dt / 1e12, "unit": "TOP/s", "cores": threads(),
+               "kind": "oracle",
+               "sample": f"the same series on the first {rows} rows of each of the {M} streams "
+                         f"(a permutation of their {rows * N} outputs); {dt:.2f} s wall"}
+    achieved = issued / (t * 1e-3) / 1e12
+    line = base_line(useful / (t * 1e-3) / 1e12, "TOP/s", args.steps, args.warmup, t, "i8",
+                     "operation series: M=4 streams of 4096x4096 int8 U[-127,127] times a shared "
+                     "4096x4096 operand, then scale U[-100,100) and add U[-1000,1000) per position, "
+                     "then a random permutation of the 4096x4096 positions, on the entangled words; "
+                     "one disentangle + check",
+                     {"M": M, "n": n, "K": K, "N": N, "l": p.l, "k": p.k, "w": 64,
+                      "out_dtype": "int32"})
+    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
+                        "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None,
+                        "scope": "whole step: GEMM head and permutation gather"}
+    line["cpu_baseline"] = cpu
+    line["fused_gemm_ms"] = t_gemm
+    line["series_overhead_pct"] = 100.0 * (t / t_gemm - 1.0)
+    return line
+
+
 def batch_problems(ne, ne_synth, np, torch, dev, recipe):
     probs = []
     useful = issued = 0.0
@@ -464,7 +547,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress"], default="gemm")
+    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series"], default="gemm")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -484,7 +567,8 @@ def main():
     if args.traffic_probe:
         traffic_probe(ne, ne_synth, np, torch, dev)
         return
-    fn = {"gemm": run_gemm, "conv": run_conv, "batch": run_batch, "stress": run_stress}
+    fn = {"gemm": run_gemm, "conv": run_conv, "batch": run_batch, "stress": run_stress,
+          "series": run_series}
     line = fn[args.workload](args, ne, ne_synth, np, torch, dev)
     print(json.dumps(line), flush=True)
 

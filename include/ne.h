@@ -316,6 +316,92 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
  */
 int64_t ne_permute_workspace(int64_t N, int32_t M, int32_t c_dtype);
 
+/* ------------------------------------------------------- operation series */
+
+#define NE_SERIES_GEMM 0
+#define NE_SERIES_CONV 1
+#define NE_SERIES_SCALE_ADD 2
+#define NE_SERIES_PERMUTE 3
+
+/*
+ * One operation of a series applied consecutively to the entangled streams
+ * before a single disentanglement (section II), described by its a-priori
+ * bounds:
+ *   NE_SERIES_GEMM       length = K (contraction length), operand_max >= |G|
+ *   NE_SERIES_CONV       length = taps N,                 operand_max >= |g|
+ *   NE_SERIES_SCALE_ADD  length >= |scale|,               operand_max >= |add|
+ *   NE_SERIES_PERMUTE    both ignored
+ */
+typedef struct ne_series_op {
+    int32_t kind, reserved;
+    int64_t length, operand_max;
+} ne_series_op_t;
+
+/*
+ * Range composition of a series.  The output condition of section III-C,
+ * |d| <= D, applies to the series' final output only: every operation is
+ * linear modulo 2^64 (the + constant entering self-entangled), so the words
+ * after the last operation are E(d) mod 2^64 even where intermediate values
+ * leave the range.  With B_0 = c_max (|inputs| <= c_max):
+ *     GEMM, conv:  B_{i+1} = B_i * length * operand_max
+ *     scale/add:   B_{i+1} = B_i * length + operand_max
+ *     permute:     B_{i+1} = B_i
+ *   eps_bits  host, [n_ops] int32, or NULL: for operation i, the eps_bits
+ *             argument of ne_lsb_gemm / ne_lsb_circconv for the entangled
+ *             words entering it: the smallest b with (2^l + 1) B_i <
+ *             2^(b-1), at most 64 (words that may have wrapped need all 64).
+ *   out_max   host, or NULL: B_{n_ops}, saturated at INT64_MAX.
+ * Returns NE_ERANGE when B_{n_ops} > D (outputs are still written), and
+ * NE_EINVAL for invalid parameters, c_max < 0, n_ops < 0, ops == NULL with
+ * n_ops > 0, an unknown kind or a negative bound.  Host arithmetic only (no
+ * device work; callable without a GPU).
+ */
+int ne_series_range(const ne_params_t *p, int64_t c_max, int32_t n_ops,
+                    const ne_series_op_t *ops, int32_t *eps_bits, int64_t *out_max);
+
+/*
+ * The series GEMM -> scale / add -> permutation on the entangled streams
+ * with one disentanglement at the end (section II's series; the + constant
+ * self-entangled as in the footnote of section III-A):
+ *     delta1[m] = eps[m] * G,   eps[m] = c[m] + 2^l c[(m-1) mod M]
+ *     delta2[m][q] = scale[q] * delta1[m][q] + (2^l + 1) * add[q]
+ *     delta3[m][q] = delta2[m][perm[q]]
+ *     d_hat, flags = disentanglement and check of delta3 (as
+ *                    ne_disentangle_check, r = p->r_check)
+ * (all mod 2^64), q = row * N + col indexing the n * N outputs of a stream.
+ * Two launches: the GEMM on int8 matrix cores as in ne_gemm_fused, with
+ * scale and add applied to the entangled words in its epilogue, writes
+ * delta2 into the workspace position-major (the M words of a position side
+ * by side, [n * N][M]); the second reads one such row per output position
+ * at perm[q], disentangles and checks.  The words stay entangled from the
+ * prologue of the first launch to the check of the second.
+ *   c, Gt, n, K, N  as for ne_gemm_fused; n * N <= 2^31 - 1.
+ *   scale, add      device, [n * N] int64, or NULL (1 and 0).
+ *   perm            device, [n * N] int32, a bijection of 0..n*N-1 (values
+ *                   out of range are clamped, never read out of bounds).
+ *   scale_max, add_max  bounds on |scale| and |add| (ignored for NULL);
+ *                   NE_ERANGE unless K * 128 * 128 * scale_max + add_max
+ *                   <= D.  The library cannot read device data before the
+ *                   launch, so it trusts them.
+ *   d_hat           device, [M][n * N] of out_dtype (NE_I32 or NE_I64).
+ *   flags           device, [ceil(n * N / 32)] uint32, or NULL.
+ *   n_bad           device counter (incremented), or NULL.
+ *   workspace       device, ne_series_workspace(n, N, M) bytes, 16-byte
+ *                   aligned, caller-owned, no overlap with any other
+ *                   argument; contents on entry irrelevant.  Too small is
+ *                   NE_EINVAL.
+ */
+int ne_series_gemm_scale_permute(const int8_t *c, const int8_t *Gt, const int64_t *scale,
+                                 const int64_t *add, const int32_t *perm, int64_t scale_max,
+                                 int64_t add_max, void *d_hat, int32_t out_dtype,
+                                 uint32_t *flags, unsigned long long *n_bad, int64_t n,
+                                 int64_t K, int64_t N, const ne_params_t *p, void *workspace,
+                                 int64_t workspace_bytes, ne_stream_t stream);
+
+/* Workspace bytes of ne_series_gemm_scale_permute: n * N * M * 8; 0 for
+ * invalid sizes or M outside 3..8. */
+int64_t ne_series_workspace(int64_t n, int64_t N, int32_t M);
+
 /* ------------------------------------------------------------------ batch */
 
 #define NE_OP_GEMM 0

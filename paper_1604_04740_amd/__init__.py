@@ -28,6 +28,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libne.so")
 
 NE_I8, NE_I32, NE_I64 = 1, 4, 8
+NE_OK, NE_EINVAL, NE_ERANGE, NE_EALIAS, NE_EALIGN, NE_EUNSUP, NE_ELAUNCH = 0, -1, -2, -3, -4, -5, -6
 _DT = {torch.int8: NE_I8, torch.int32: NE_I32, torch.int64: NE_I64}
 
 
@@ -58,6 +59,14 @@ class _Problem(ctypes.Structure):
 
 class _Tuning(ctypes.Structure):
     _fields_ = [("gemm_bn", (ctypes.c_int32 * 3) * 6), ("perm_chunk", (ctypes.c_int64 * 3) * 6)]
+
+
+NE_SERIES_GEMM, NE_SERIES_CONV, NE_SERIES_SCALE_ADD, NE_SERIES_PERMUTE = 0, 1, 2, 3
+
+
+class _SeriesOp(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("length", ctypes.c_int64), ("operand_max", ctypes.c_int64)]
 
 
 class _Inject(ctypes.Structure):
@@ -99,6 +108,12 @@ def lib():
             "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
                                         _vp, _i64, _vp], ctypes.c_int),
             "ne_permute_workspace": ([_i64, _i32, _i32], _i64),
+            "ne_series_range": ([P, _i64, _i32, ctypes.POINTER(_SeriesOp),
+                                 ctypes.POINTER(_i32), ctypes.POINTER(_i64)], ctypes.c_int),
+            "ne_series_gemm_scale_permute": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp,
+                                              _vp, _i64, _i64, _i64, P, _vp, _i64, _vp],
+                                             ctypes.c_int),
+            "ne_series_workspace": ([_i64, _i64, _i32], _i64),
             "ne_batch_plan": ([ctypes.POINTER(_Problem), _i32, ctypes.POINTER(_Tuning), _vp, _i64,
                                ctypes.POINTER(_i64), ctypes.POINTER(_vp)], ctypes.c_int),
             "ne_batch_run": ([_vp, _vp], ctypes.c_int),
@@ -434,6 +449,67 @@ def ne_permute_scale_fused(c: torch.Tensor, perm: torch.Tensor, scale: torch.Ten
                                      _opt(ws, "workspace", None),
                                      ws.numel() * ws.element_size() if ws is not None else 0,
                                      _stream()), "ne_permute_scale_fused")
+    return out, flags, n_bad
+
+
+# ------------------------------------------------------- operation series
+
+def ne_series_range(p: Params, c_max: int, ops):
+    """ops: (kind, length, operand_max) tuples (NE_SERIES_*).  Returns
+    (eps_bits per operation, bound on the final output, whether it is within
+    the entangled range).  Invalid arguments raise NEError."""
+    n = len(ops)
+    arr = (_SeriesOp * max(n, 1))()
+    for i, (kind, length, omax) in enumerate(ops):
+        arr[i].kind, arr[i].length, arr[i].operand_max = kind, length, omax
+    bits = (ctypes.c_int32 * max(n, 1))()
+    out = ctypes.c_int64()
+    rc = lib().ne_series_range(ctypes.byref(p), c_max, n, arr, bits, ctypes.byref(out))
+    if rc not in (0, NE_ERANGE):
+        raise NEError(rc, "ne_series_range")
+    return [bits[i] for i in range(n)], out.value, rc == 0
+
+
+def ne_series_workspace(n: int, N: int, M: int) -> int:
+    return int(lib().ne_series_workspace(n, N, M))
+
+
+def ne_series_gemm_scale_permute(c: torch.Tensor, Gt: torch.Tensor, scale: torch.Tensor | None,
+                                 add: torch.Tensor | None, perm: torch.Tensor, p: Params, *,
+                                 scale_max: int | None = None, add_max: int | None = None,
+                                 out_dtype=torch.int32, out: torch.Tensor | None = None,
+                                 flags: bool | torch.Tensor = True,
+                                 n_bad: torch.Tensor | None = None,
+                                 workspace: torch.Tensor | None = None):
+    """c: [M, n, K] int8, Gt: [N, K] int8, scale/add [n*N] int64 or None,
+    perm [n*N] int32 -> (d_hat [M, n*N], flags [ceil(n*N/32)], n_bad).
+    scale_max / add_max bound |scale| / |add| and are required with them."""
+    M, n, K = c.shape
+    N, K2 = Gt.shape
+    Q = n * N
+    if M != p.M or K2 != K or perm.shape != (Q,):
+        raise ValueError("shape mismatch")
+    if (scale is not None and scale_max is None) or (add is not None and add_max is None):
+        raise ValueError("scale_max / add_max are required with scale / add")
+    if out is None:
+        out = torch.empty((M, Q), dtype=out_dtype, device=c.device)
+    if flags is True:
+        flags = torch.empty(((Q + 31) // 32,), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    need = ne_series_workspace(n, N, M)
+    if workspace is None:
+        workspace = torch.empty((max(need, 16) // 8,), dtype=torch.int64, device=c.device)
+    _ok(lib().ne_series_gemm_scale_permute(
+        _dev(c, "c", torch.int8), _dev(Gt, "Gt", torch.int8), _opt(scale, "scale", torch.int64),
+        _opt(add, "add", torch.int64), _dev(perm, "perm", torch.int32),
+        scale_max if scale is not None else 1, add_max if add is not None else 0,
+        _dev(out, "out", out_dtype), _DT[out_dtype], _opt(flags, "flags", torch.int32),
+        _dev(n_bad, "n_bad", torch.int64), n, K, N, ctypes.byref(p),
+        _dev(workspace, "workspace"), workspace.numel() * workspace.element_size(),
+        _stream()), "ne_series_gemm_scale_permute")
     return out, flags, n_bad
 
 

@@ -424,4 +424,105 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
                                       hs(stream));
 }
 
+int ne_series_range(const ne_params_t *p, int64_t c_max, int32_t n_ops, const ne_series_op_t *ops,
+                    int32_t *eps_bits, int64_t *out_max)
+{
+    int64_t D = 0;
+    if (ne_range_bound(p, &D) != NE_OK || c_max < 0 || n_ops < 0 || (n_ops > 0 && !ops))
+        return NE_EINVAL;
+    for (int32_t i = 0; i < n_ops; ++i)
+        if (ops[i].kind < NE_SERIES_GEMM || ops[i].kind > NE_SERIES_PERMUTE || ops[i].length < 0 ||
+            ops[i].operand_max < 0)
+            return NE_EINVAL;
+    // Bounds are exact integers, saturated at 2^126 (far above any D).
+    typedef unsigned __int128 u128;
+    const u128 cap = (u128)1 << 126;
+    auto mul = [cap](u128 a, u128 b) -> u128 {
+        if (a == 0 || b == 0)
+            return 0;
+        return a > cap / b ? cap : a * b;
+    };
+    u128 B = (u128)c_max;
+    for (int32_t i = 0; i < n_ops; ++i) {
+        if (eps_bits) {
+            // entangled words entering step i: |eps| <= (2^l + 1) B < 2^(bits-1)
+            const u128 e = mul(B, ((u128)1 << p->l) + 1);
+            int bits = 1;
+            while (bits < 64 && ((u128)1 << (bits - 1)) <= e)
+                ++bits;
+            eps_bits[i] = bits;
+        }
+        const ne_series_op_t &o = ops[i];
+        switch (o.kind) {
+        case NE_SERIES_GEMM:
+        case NE_SERIES_CONV: B = mul(mul(B, (u128)o.length), (u128)o.operand_max); break;
+        case NE_SERIES_SCALE_ADD: {
+            const u128 t = mul(B, (u128)o.length) + (u128)o.operand_max;
+            B = t > cap ? cap : t;
+            break;
+        }
+        default: break; // a permutation keeps the bound
+        }
+    }
+    if (out_max)
+        *out_max = B > (u128)INT64_MAX ? INT64_MAX : (int64_t)B;
+    return B > (u128)D ? NE_ERANGE : NE_OK;
+}
+
+int64_t ne_series_workspace(int64_t n, int64_t N, int32_t M)
+{
+    if (n < 0 || N < 0 || M < 3 || M > kMaxStreamsFused || (N > 0 && n > INT64_MAX / 8 / M / N))
+        return 0;
+    return n * N * M * 8;
+}
+
+int ne_series_gemm_scale_permute(const int8_t *c, const int8_t *Gt, const int64_t *scale,
+                                 const int64_t *add, const int32_t *perm, int64_t scale_max,
+                                 int64_t add_max, void *d_hat, int32_t out_dtype, uint32_t *flags,
+                                 unsigned long long *n_bad, int64_t n, int64_t K, int64_t N,
+                                 const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                                 ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsFused);
+    if (rc)
+        return rc;
+    if (n < 0 || K < 0 || N < 0 || K > kMaxK || (out_dtype != NE_I32 && out_dtype != NE_I64) ||
+        (scale && scale_max < 0) || (add && add_max < 0))
+        return NE_EINVAL;
+    if (N > 0 && n > 0x7fffffff / N)
+        return NE_EINVAL; // positions are int32 permutation indices
+    const int64_t s_max = scale ? scale_max : 1, a_max = add ? add_max : 0;
+    int64_t D = 0;
+    ne_range_bound(p, &D);
+    // a-priori bound K * 128 * 128 * s_max + a_max <= D, without overflow
+    if (a_max > D || (K > 0 && s_max > (D - a_max) / (K * 128 * 128)))
+        return NE_ERANGE;
+    const int64_t Q = n * N;
+    if (Q == 0)
+        return NE_OK;
+    if (((!c || !Gt) && K > 0) || !perm || !d_hat || !workspace)
+        return NE_EINVAL;
+    const int64_t need = ne_series_workspace(n, N, p->M);
+    if (workspace_bytes < need)
+        return NE_EINVAL;
+    const int64_t ob = p->M * Q * out_dtype, fb = ((Q + 31) / 32) * 4;
+    const int64_t cb = p->M * n * K, gb = N * K;
+    if (overlap(c, cb, d_hat, ob) || overlap(Gt, gb, d_hat, ob) || overlap(perm, Q * 4, d_hat, ob) ||
+        overlap(scale, Q * 8, d_hat, ob) || overlap(add, Q * 8, d_hat, ob) ||
+        overlap(flags, fb, d_hat, ob) || overlap(workspace, need, c, cb) ||
+        overlap(workspace, need, Gt, gb) || overlap(workspace, need, perm, Q * 4) ||
+        overlap(workspace, need, scale, Q * 8) || overlap(workspace, need, add, Q * 8) ||
+        overlap(workspace, need, d_hat, ob) || overlap(workspace, need, flags, fb))
+        return NE_EALIAS;
+    if ((uintptr_t)workspace % 16 || (uintptr_t)d_hat % out_dtype || (uintptr_t)perm % 4 ||
+        (uintptr_t)scale % 8 || (uintptr_t)add % 8 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    rc = launch_series_gemm(c, Gt, scale, add, (int64_t *)workspace, n, K, N, p->M, p->l,
+                            p->r_check, hs(stream));
+    if (rc)
+        return rc;
+    return launch_permute_rows_check((const int64_t *)workspace, perm, d_hat, out_dtype == NE_I64,
+                                     flags, n_bad, Q, p->M, p->l, p->r_check, hs(stream));
+}
+
 } // extern "C"

@@ -210,7 +210,28 @@ template <int M> struct PermFusedL {
     }
 };
 
+// Gather of entangled rows (the position-major output of a series' GEMM
+// head), then disentangle and check.
+template <int M> struct PermRowsL {
+    static int run(const int64_t *rows, const int32_t *perm, void *dhat, int out64,
+                   uint32_t *flags, unsigned long long *nb, int64_t N, int l, int r,
+                   hipStream_t s)
+    {
+        k_permute_scale_fused<M, int64_t, true><<<grid_for(N, kThreads), kThreads, 0, s>>>(
+            nullptr, (const uint64_t *)rows, perm, nullptr, nullptr, dhat, out64, flags, nb, N, l,
+            r);
+        return launch_status();
+    }
+};
+
 } // namespace
+
+int launch_permute_rows_check(const int64_t *rows, const int32_t *perm, void *dhat, int out64,
+                              uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                              int r, hipStream_t s)
+{
+    return dispatch_m<PermRowsL>(M, rows, perm, dhat, out64, flags, n_bad, N, l, r, s);
+}
 
 int64_t permute_rows_bytes(int64_t N, int M, int c_dtype)
 {

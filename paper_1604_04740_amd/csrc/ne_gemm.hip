@@ -83,6 +83,25 @@ int launch_fused_m(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uin
 }
 
 template <int M>
+int launch_series_m(const int8_t *c, const int8_t *Bt, const int64_t *scale, const int64_t *add,
+                    int64_t *rows, int64_t n, int64_t K, int64_t N, int l, int r, hipStream_t s)
+{
+    using V = SeriesV<M>;
+    typename V::Args a{};
+    a.Bt = Bt;
+    a.K = K;
+    a.N = N;
+    a.c = c;
+    a.n = n;
+    a.l = l;
+    a.r = r;
+    a.scale = scale;
+    a.add = add;
+    a.rows = rows;
+    return launch<V>(a, n, (K % 16 == 0) && aligned16(c) && aligned16(Bt), s);
+}
+
+template <int M>
 int launch_abft_m(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
                   unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, hipStream_t s)
 {
@@ -140,6 +159,21 @@ int launch_gemm_fused(const int8_t *c, const int8_t *Bt, void *dhat, int out64, 
     case 6: return launch_fused_m<6>(c, Bt, dhat, out64, flags, n_bad, n, K, N, l, r, inj, s);
     case 7: return launch_fused_m<7>(c, Bt, dhat, out64, flags, n_bad, n, K, N, l, r, inj, s);
     case 8: return launch_fused_m<8>(c, Bt, dhat, out64, flags, n_bad, n, K, N, l, r, inj, s);
+    default: return NE_EUNSUP;
+    }
+}
+
+int launch_series_gemm(const int8_t *c, const int8_t *Bt, const int64_t *scale, const int64_t *add,
+                       int64_t *rows, int64_t n, int64_t K, int64_t N, int M, int l, int r,
+                       hipStream_t s)
+{
+    switch (M) {
+    case 3: return launch_series_m<3>(c, Bt, scale, add, rows, n, K, N, l, r, s);
+    case 4: return launch_series_m<4>(c, Bt, scale, add, rows, n, K, N, l, r, s);
+    case 5: return launch_series_m<5>(c, Bt, scale, add, rows, n, K, N, l, r, s);
+    case 6: return launch_series_m<6>(c, Bt, scale, add, rows, n, K, N, l, r, s);
+    case 7: return launch_series_m<7>(c, Bt, scale, add, rows, n, K, N, l, r, s);
+    case 8: return launch_series_m<8>(c, Bt, scale, add, rows, n, K, N, l, r, s);
     default: return NE_EUNSUP;
     }
 }

@@ -1,7 +1,7 @@
 // ne_gemm_impl.h -- int8 matrix-core GEMM device code for gfx950 (shared by
 // the GEMM entry points and the batched persistent kernel).
 //
-// One kernel template, four variants:
+// One kernel template, five variants:
 //   PlainV     C = A * B, int8 -> int32 (the fault-intolerant baseline)
 //   EpsV<L>    delta = eps * G on generic int64 words: each word is split
 //              into L signed int8 digits in the prologue, one exact int32
@@ -12,6 +12,10 @@
 //              c_{m-1}), two independent int32 products per stream,
 //              delta_m = P_lo + 2^l P_hi, then disentangle and check in the
 //              epilogue (section III-C); delta never leaves registers
+//   SeriesV<M> the GEMM at the head of an operation series (section II):
+//              FusedV's prologue and products, then scale and add on the
+//              entangled words in the epilogue, stored position-major for
+//              the operation that follows; no disentangle
 //   AbftV<M>   checksum-stream ABFT of section II-A: the checksum row
 //              sum_m c_m (two int8 digits) is built in the prologue and
 //              multiplied alongside the M streams; the epilogue checks
@@ -796,6 +800,56 @@ struct FusedV {
             fe = lo;
         }
         epi(g, acc, row0, col0, wm, wn, lane, fb, fe);
+    }
+};
+
+// GEMM head of a series: the entangled products of FusedV, then
+//     delta[q] = scale[q] * delta[q] + (2^l + 1) * add[q]   (mod 2^64)
+// on every stream, stored as rows[q][s] (slot s = stream (r + s) mod M): a
+// lane holds every stream of its positions, so each store is M contiguous
+// words and a half-wavefront writes 32 * M contiguous words.
+template <int M>
+struct SeriesV : FusedV<M> {
+    using Base = FusedV<M>;
+    using Base::BMS;
+    using Base::CB;
+    using Base::P;
+    using Base::RB;
+    struct Args : Base::Args {
+        const int64_t *scale;
+        const int64_t *add;
+        int64_t *rows;
+    };
+
+    __device__ __forceinline__ static void epilogue(const Args &g, v16i (&acc)[P][RB][CB],
+                                                    int64_t row0, int64_t col0, int wm, int wn,
+                                                    int lane)
+    {
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int64_t col = col0 + (wn * CB + j) * 32 + acc_col(lane);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * 32 + acc_row(r, lane);
+                uint64_t d[M];
+#pragma unroll
+                for (int s = 0; s < M; ++s) {
+                    int lo, hi;
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(acc[s][0][j][r]));
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(acc[M + s][0][j][r]));
+                    d[s] = (uint64_t)(int64_t)lo + ((uint64_t)(int64_t)hi << g.l);
+                }
+                if (row < g.n && col < g.N) {
+                    const int64_t q = row * g.N + col;
+                    const uint64_t sc = g.scale ? (uint64_t)g.scale[q] : 1u;
+                    const uint64_t a = g.add ? (uint64_t)entangle_word(g.add[q], g.add[q], g.l) : 0u;
+#pragma unroll
+                    for (int s = 0; s < M; ++s)
+                        g.rows[q * M + s] = (int64_t)(sc * d[s] + a);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
     }
 };
 

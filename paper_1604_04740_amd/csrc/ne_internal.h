@@ -40,6 +40,11 @@ int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
                                const int64_t *scale, const int64_t *add, void *dhat, int out64,
                                uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
                                int r, void *rows, hipStream_t s);
+// Gather of position-major entangled rows [N][M] (no entangle), then
+// disentangle and check.
+int launch_permute_rows_check(const int64_t *rows, const int32_t *perm, void *dhat, int out64,
+                              uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
+                              int r, hipStream_t s);
 
 // ---- matrix-core GEMMs (ne_gemm.hip) ----
 int launch_gemm_plain(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, int64_t K,
@@ -49,6 +54,11 @@ int launch_gemm_eps(const int64_t *eps, int digits, const int8_t *Bt, int64_t *d
 int launch_gemm_fused(const int8_t *c, const int8_t *Bt, void *dhat, int out64, uint32_t *flags,
                       unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M, int l,
                       int r, const ne_inject_t *inj, hipStream_t s);
+// GEMM head of a series: entangled products, scale / add, position-major
+// rows [n * N][M] out.
+int launch_series_gemm(const int8_t *c, const int8_t *Bt, const int64_t *scale, const int64_t *add,
+                       int64_t *rows, int64_t n, int64_t K, int64_t N, int M, int l, int r,
+                       hipStream_t s);
 int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
                      unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M,
                      hipStream_t s);

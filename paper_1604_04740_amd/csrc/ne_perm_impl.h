@@ -49,7 +49,9 @@ __device__ __forceinline__ void perm_pack_range(const T *__restrict__ c,
 // words (64 consecutive positions).
 // Positions [first, last) (first a multiple of 64), visited by the
 // workgroup's 256 threads starting at `first + start`, step `stride`.
-template <int M, typename T>
+// ENT: the rows already hold entangled 64-bit words (the output of an
+// earlier operation of a series), so the entangle step is skipped.
+template <int M, typename T, bool ENT = false>
 __device__ __forceinline__ void perm_fused_range(
     const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
@@ -107,9 +109,14 @@ __device__ __forceinline__ void perm_fused_range(
                 const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
                 int64_t d[M], o[M];
 #pragma unroll
-                for (int s = 0; s < M; ++s)
-                    d[s] = (int64_t)(sc * (uint64_t)entangle_word(v[u][s], v[u][(s + M - 1) % M], l) +
-                                     a);
+                for (int s = 0; s < M; ++s) {
+                    if constexpr (ENT)
+                        d[s] = (int64_t)(sc * (uint64_t)v[u][s] + a);
+                    else
+                        d[s] = (int64_t)(sc * (uint64_t)entangle_word(v[u][s],
+                                                                      v[u][(s + M - 1) % M], l) +
+                                         a);
+                }
                 f = disentangle_rot<M>(d, l, o);
 #pragma unroll
                 for (int s = 0; s < M; ++s) {
@@ -144,14 +151,14 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_pack(const T *__restrict_
                           (int64_t)gridDim.x * kPermThreads);
 }
 
-template <int M, typename T>
+template <int M, typename T, bool ENT = false>
 __global__ __launch_bounds__(kPermThreads) void k_permute_scale_fused(
     const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
     const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
     int out64, uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N,
     int l, int r)
 {
-    perm_fused_range<M, T>(c, rows, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
+    perm_fused_range<M, T, ENT>(c, rows, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
                            (int64_t)blockIdx.x * kPermThreads,
                            (int64_t)gridDim.x * kPermThreads);
 }

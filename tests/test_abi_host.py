@@ -137,3 +137,66 @@ def test_permute_workspace_size_and_rejection(ne):
     rc = L.ne_permute_scale_fused(c, 1, perm, None, None, d, 8, None, None, 1000, ctypes.byref(p),
                                   c, 1000 * 8, None)
     assert rc == -3  # overlaps the inputs
+
+
+def test_series_range_matches_oracle(ne, orc):
+    """ne_series_range composes the a-priori bound exactly as the oracle's
+    series bound, reports NE_ERANGE exactly when it exceeds D, and gives
+    eps_bits that hold the entangled words entering every operation."""
+    G_, C_, S_, P_ = ne.NE_SERIES_GEMM, ne.NE_SERIES_CONV, ne.NE_SERIES_SCALE_ADD, ne.NE_SERIES_PERMUTE
+    cases = [
+        (127, [(G_, 4096, 127), (S_, 3, 1000), (P_, 0, 0)]),
+        (127, [(G_, 64, 128), (P_, 0, 0), (C_, 16, 64), (S_, 1, 5)]),
+        (1024, [(C_, 16384, 64)]),
+        (5, [(S_, 1, 0), (P_, 0, 0)]),
+        (127, [(G_, 4096, 127), (G_, 4096, 127)]),   # far beyond D: words wrap
+        (0, [(G_, 10, 10)]),
+        (127, []),
+    ]
+    kind = {G_: "gemm", C_: "conv", S_: "scale_add"}
+    for M in (3, 4, 8):
+        p = ne.ne_params_default(M)
+        D = ne.ne_range_bound(p)
+        for c_max, ops in cases:
+            oops = [(kind[k], a, b) if k != P_ else ("permute",) for k, a, b in ops]
+            bits, out_max, ok = ne.ne_series_range(p, c_max, ops)
+            B = orc.series_bound(c_max, oops)
+            assert out_max == min(B, 2**63 - 1)
+            assert ok == (B <= D)
+            for i in range(len(ops)):
+                e = (2**p.l + 1) * orc.series_bound(c_max, oops[:i])
+                want = min(64, e.bit_length() + 1)
+                assert bits[i] == want, (M, c_max, ops, i)
+                assert bits[i] == 64 or e < 2 ** (bits[i] - 1)
+
+
+def test_series_argument_errors(ne):
+    L = ne.lib()
+    p = ne.ne_params_default(4)
+    ops = (ne._SeriesOp * 1)()
+    ops[0].kind, ops[0].length, ops[0].operand_max = 7, 1, 1
+    assert L.ne_series_range(ctypes.byref(p), 1, 1, ops, None, None) == ne.NE_EINVAL
+    ops[0].kind, ops[0].length = ne.NE_SERIES_GEMM, -1
+    assert L.ne_series_range(ctypes.byref(p), 1, 1, ops, None, None) == ne.NE_EINVAL
+    assert L.ne_series_range(ctypes.byref(p), -1, 0, None, None, None) == ne.NE_EINVAL
+    assert L.ne_series_range(ctypes.byref(p), 1, 1, None, None, None) == ne.NE_EINVAL
+    assert L.ne_series_range(ctypes.byref(p), 1, 0, None, None, None) == ne.NE_OK
+    assert ne.ne_series_workspace(4096, 4096, 4) == 4096 * 4096 * 4 * 8
+    assert ne.ne_series_workspace(4, 4, 9) == 0 and ne.ne_series_workspace(-1, 4, 4) == 0
+    # fused series: range, sizes and workspace rejected before any launch
+    fake = ctypes.c_void_p(1 << 20)
+    D = ne.ne_range_bound(p)  # 2^47 - 2^31 at M = 4
+    K = 4096
+    s_ok = D // (K * 128 * 128)
+    args = lambda smax, amax, n, Kk, N, ws, wsb: L.ne_series_gemm_scale_permute(
+        fake, fake, fake, fake, fake, smax, amax, fake, ne.NE_I32, None, None, n, Kk, N,
+        ctypes.byref(p), ws, wsb, None)
+    assert args(s_ok + 1, 0, 64, K, 64, fake, 1 << 30) == ne.NE_ERANGE
+    assert args(1, D + 1, 64, K, 64, fake, 1 << 30) == ne.NE_ERANGE
+    assert args(-1, 0, 64, K, 64, fake, 1 << 30) == ne.NE_EINVAL
+    assert args(1, 0, 1 << 16, K, 1 << 16, fake, 1 << 62) == ne.NE_EINVAL  # n N > 2^31 - 1
+    assert args(1, 0, 64, K, 64, None, 1 << 30) == ne.NE_EINVAL
+    assert args(1, 0, 64, K, 64, fake, 64 * 64 * 4 * 8 - 1) == ne.NE_EINVAL
+    assert args(1, 0, 64, K, 64, ctypes.c_void_p((1 << 20) + 8), 1 << 30) in (ne.NE_EALIAS,
+                                                                              ne.NE_EALIGN)
+    assert args(1, 0, 0, K, 64, None, 0) == ne.NE_OK
