@@ -77,11 +77,25 @@ __device__ __forceinline__ void perm_fused_range(
         int64_t v[U][M]; // v[u][s] = input of stream (r + s) mod M, i.e. slot order
         if (rows) {
             uint64_t q[U][Q];
+            if constexpr (ENT && Q % 2 == 0) {
+                // entangled rows start 16-byte aligned: 16-byte loads
+                typedef unsigned long long v2u __attribute__((ext_vector_type(2)));
+                const v2u *rv = (const v2u *)rows;
 #pragma unroll
-            for (int u = 0; u < U; ++u)
+                for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int k = 0; k < Q; ++k)
-                    q[u][k] = rows[src[u] * Q + k];
+                    for (int k = 0; k < Q / 2; ++k) {
+                        const v2u t = rv[src[u] * (Q / 2) + k];
+                        q[u][2 * k] = t.x;
+                        q[u][2 * k + 1] = t.y;
+                    }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u)
+#pragma unroll
+                    for (int k = 0; k < Q; ++k)
+                        q[u][k] = rows[src[u] * Q + k];
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 T t[Q * 8 / sizeof(T)];
