@@ -13,6 +13,8 @@ Parity status of each function (what pins it is listed in tests/):
   params, range_bound           pinned (Table II; exhaustive tiny-w range)
   entangle, self_entangle       pinned (hand-worked example; operator E)
   gemm, circconv, permute_scale pinned (numpy / Python-int textbook results)
+  linconv, linconv_pipeline     pinned (numpy convolve; overlap-save blocks
+                                of the pinned circular convolution)
   extract, check, extract3      pinned (exhaustive tiny w, closed forms)
   abft_checksum, abft_check     pinned (sum identities, recovery)
   series_bound, series_pipeline pinned (plain series in Python integers,
@@ -68,6 +70,8 @@ def lib():
         L.ne_oracle_gemm.restype = None
         L.ne_oracle_circconv.argtypes = [_i64p, _i64p, _i64p, I, i]
         L.ne_oracle_circconv.restype = None
+        L.ne_oracle_linconv.argtypes = [_i64p, I, _i64p, I, _i64p, i]
+        L.ne_oracle_linconv.restype = None
         L.ne_oracle_permute_scale.argtypes = [_i64p, _i64p, _i64p, _i64p, _i64p, I, i]
         L.ne_oracle_permute_scale.restype = None
         L.ne_oracle_extract.argtypes = [_i64p, _i64p, i, I, i, i, i]
@@ -150,6 +154,16 @@ def circconv(x, g, w: int = 64) -> np.ndarray:
     assert x.shape == g.shape and x.ndim == 1
     y = np.empty_like(x)
     lib().ne_oracle_circconv(_p(x), _p(g), _p(y), x.size, w)
+    return y
+
+
+def linconv(x, g, w: int = 64) -> np.ndarray:
+    """y[t] = sum_j x[t-j] g[j], 0 <= t < len(x) + len(g) - 1, x zero outside
+    its range (mod 2^w)."""
+    x, g = _a64(x), _a64(g)
+    assert x.ndim == 1 and g.ndim == 1 and x.size > 0 and g.size > 0
+    y = np.empty(x.size + g.size - 1, dtype=np.int64)
+    lib().ne_oracle_linconv(_p(x), x.size, _p(g), g.size, _p(y), w)
     return y
 
 
@@ -269,6 +283,19 @@ def conv_pipeline(c, g, w: int = 64, r: int = 0):
     l, k = params(M, w)
     eps = entangle(c, w, l)
     delta = np.stack([circconv(eps[m], g, w) for m in range(M)])
+    dhat, flags, bad = extract_check(delta, w, l, r)
+    return dict(eps=eps, delta=delta, dhat=dhat, flags=flags, n_bad=bad, l=l, k=k)
+
+
+def linconv_pipeline(c, g, w: int = 64, r: int = 0):
+    """Entangle c[M][Nx], convolve every entangled stream with the L-tap
+    kernel g (linear convolution, section IV), extract without stream r and
+    check."""
+    c = _a64(c)
+    M = c.shape[0]
+    l, k = params(M, w)
+    eps = entangle(c, w, l)
+    delta = np.stack([linconv(eps[m], g, w) for m in range(M)])
     dhat, flags, bad = extract_check(delta, w, l, r)
     return dict(eps=eps, delta=delta, dhat=dhat, flags=flags, n_bad=bad, l=l, k=k)
 

@@ -204,6 +204,29 @@ void ne_oracle_circconv(const int64_t *x, const int64_t *g, int64_t *y, int64_t 
 }
 
 /*
+ * Linear convolution of one stream of Nx samples with a kernel of L taps
+ * (section IV: the convolution of a long stream with a short kernel, which
+ * the paper evaluates with overlap-save blocks):
+ *     y[t] = sum_{j=0}^{L-1} x[t - j] * g[j]   (mod 2^w),  0 <= t < Nx + L - 1,
+ * with x zero outside [0, Nx).  Direct evaluation.
+ */
+void ne_oracle_linconv(const int64_t *x, int64_t Nx, const int64_t *g, int64_t L, int64_t *y,
+                       int w)
+{
+    const int64_t Ny = Nx + L - 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < Ny; ++t) {
+        int64_t acc = 0;
+        for (int64_t j = 0; j < L; ++j) {
+            const int64_t i = t - j;
+            if (i >= 0 && i < Nx)
+                acc = add_w(acc, mul_w(x[i], g[j], w), w);
+        }
+        y[t] = acc;
+    }
+}
+
+/*
  * Fixed (data-independent) permutation followed by element-wise scaling and
  * addition of a constant (section II, op in {x, +, permutation}):
  *     y[n] = scale[n] * x[perm[n]] + add[n]   (mod 2^w).

@@ -516,3 +516,61 @@ def test_series_intermediate_wrap_tiny_w(orc):
     assert np.array_equal(res["dhat"], c[:, perm])
     res = orc.series_pipeline(c, ops[:2], w=w)
     assert not np.array_equal(res["dhat"], c[:, perm] + 50 * D)
+
+
+# ------------------------------------------------------ linear convolution
+
+def test_linconv_textbook(orc):
+    """The oracle's linear convolution equals numpy.convolve (full mode),
+    including a kernel longer than the input and a single tap."""
+    rng = np.random.default_rng(2600)
+    for nx, L in [(50, 7), (5, 12), (33, 1), (1, 1), (300, 64)]:
+        x = rng.integers(-1000, 1000, nx)
+        g = rng.integers(-64, 64, L)
+        assert np.array_equal(orc.linconv(x, g), np.convolve(x, g))
+
+
+def test_linconv_overlap_save(orc):
+    """Overlap-save (section IV's block realisation): blocks of B inputs
+    overlapping by L - 1, each circularly convolved with the zero-padded
+    kernel, keep their last B - L + 1 outputs; concatenated they are the
+    linear convolution.  Pins the linear convolution against the (separately
+    pinned) circular one."""
+    rng = np.random.default_rng(2601)
+    nx, L, B = 97, 9, 32
+    x = rng.integers(-1000, 1000, nx)
+    g = rng.integers(-64, 64, L)
+    hop = B - L + 1
+    ny = nx + L - 1
+    xp = np.concatenate([np.zeros(L - 1, np.int64), x, np.zeros(B, np.int64)])
+    gp = np.concatenate([g, np.zeros(B - L, np.int64)])
+    out = []
+    for s in range(0, ny, hop):
+        yb = orc.circconv(xp[s:s + B], gp)
+        out.append(yb[L - 1:])
+    y = np.concatenate(out)[:ny]
+    assert np.array_equal(y, orc.linconv(x, g))
+
+
+@pytest.mark.parametrize("M", [3, 8])
+def test_linconv_pipeline(orc, M):
+    """Entangled linear convolution: exact outputs (numpy.convolve per
+    stream), entangled words E(d), no flags on clean data, and a bit flipped
+    in one stream's output flagged at exactly that position."""
+    l, k = orc.params(M, 64)
+    rng = np.random.default_rng(2602 + M)
+    nx, L = 120, 17
+    c = rng.integers(-(1 << 14), 1 << 14, (M, nx))
+    g = rng.integers(-128, 128, L)
+    res = orc.linconv_pipeline(c, g)
+    want = np.stack([np.convolve(c[m], g) for m in range(M)])
+    assert np.array_equal(res["dhat"], want)
+    assert res["n_bad"] == 0
+    for m in range(M):
+        ent = [_wrap(int(want[m][t]) + (int(want[(m - 1) % M][t]) << l), 64)
+               for t in range(want.shape[1])]
+        assert [int(v) for v in res["delta"][m]] == ent
+    delta = res["delta"].copy()
+    delta[M - 1, 40] ^= 1 << 33
+    _, flags, bad = orc.extract_check(delta, 64, l, 0)
+    assert bad == 1 and flags[40] and flags.sum() == 1
