@@ -374,6 +374,105 @@ def run_series(args, ne, ne_synth, np, torch, dev):
     return line
 
 
+def run_linconv(args, ne, ne_synth, np, torch, dev):
+    """Linear convolution of long streams with a short kernel (the paper's
+    convolution experiment: 10^6 samples per stream, kernels of 100 to 4500
+    taps, M = 3 and 8), fused with entangle, disentangle and check.  The line
+    is M = 8, 4500 taps; the other corners are extra fields."""
+    import oracle
+
+    seed = ne_synth.BASE_SEED + 6
+    nx = 1_000_000
+
+    def inputs(M, L):
+        c = ne_synth.uniform_int(seed, 1, (M, nx), -(1 << 14), 1 << 14).astype(np.int32)
+        g = ne_synth.uniform_int(seed, 2, (L,), -128, 128).astype(np.int8)
+        return c, g
+
+    def measure(M, L, with_plain):
+        c, g = inputs(M, L)
+        p = ne.ne_params_default(M)
+        c_d, g_d = torch.from_numpy(c).to(dev), torch.from_numpy(g).to(dev)
+        no = nx + L - 1
+        out = torch.empty((M, no), dtype=torch.int32, device=dev)
+        fl = torch.empty(((no + 31) // 32,), dtype=torch.int32, device=dev)
+        nb = torch.zeros((1,), dtype=torch.int64, device=dev)
+        t = time_launches(lambda: ne.ne_linconv_fused(c_d, g_d, p, c_bits=15, out_dtype=torch.int32,
+                                                      out=out, flags=fl, n_bad=nb),
+                          args.steps, args.warmup, torch)
+        assert int(nb.item()) == 0, "clean run flagged positions"
+        res = {"M": M, "taps": L, "ms": t, "useful_tops": 2.0 * M * nx * L / (t * 1e-3) / 1e12}
+        if with_plain:
+            # the same convolutions without entanglement: M plain streams on
+            # the staged kernel (one product per stream instead of two)
+            c64 = c_d.to(torch.int64)
+            d = torch.empty((M, no), dtype=torch.int64, device=dev)
+            tp = time_launches(lambda: ne.ne_lsb_linconv(c64, 15, g_d, p, out=d), args.steps,
+                               args.warmup, torch)
+            assert torch.equal(d.to(torch.int32), out), "fused d_hat differs from the plain conv"
+            res["plain_ms"] = tp
+            res["overhead_vs_plain_pct"] = 100.0 * (t / tp - 1.0)
+            del c64, d
+        return res, c, g, out
+
+    log("fused linear convolution, M = 8, 4500 taps")
+    main, c, g, out = measure(8, 4500, True)
+    M, L = 8, 4500
+    log("sampled parity against the oracle")
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(5)
+    g64 = g.astype(np.int64)
+    for t in rng.integers(0, nx + L - 1, 4):
+        lo = int(t) - (L - 1)
+        a, b = max(lo, 0), min(int(t) + 1, nx)
+        seg = np.zeros((M, L), np.int64)
+        seg[:, a - lo:b - lo] = c[:, a:b]
+        want = np.array([oracle.linconv(seg[m], g64)[L - 1] for m in range(M)])
+        assert np.array_equal(got[:, t].astype(np.int64), want), "linear conv differs from oracle"
+    del got
+    corners = []
+    for Mc, Lc in [(8, 100), (3, 4500), (3, 100)]:
+        log(f"fused linear convolution, M = {Mc}, {Lc} taps")
+        corners.append(measure(Mc, Lc, True)[0])
+    t = main["ms"]
+    no = nx + L - 1
+    blocks = (no + 1023) // 1024
+    ksteps = (L + 32 + 31) // 32
+    digits = 2
+    issued = blocks * ksteps * 2 * M * digits * 2.0 * 32 ** 3
+    achieved = issued / (t * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        S = 2048
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.linconv_pipeline(c[:, :S].astype(np.int64), g64)
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or S >= nx:
+                break
+            S = min(nx, max(S * 2, int(S * args.cpu_seconds / max(dt, 1e-3) * 1.1)))
+        assert ref["n_bad"] == 0
+        cpu = {"value": 2.0 * M * S * L / dt / 1e12, "unit": "TOP/s", "cores": threads(),
+               "kind": "oracle",
+               "sample": f"the first {S} samples of each of the {M} streams, all {L} taps "
+                         f"(entangle + linear conv on entangled words + extract + check); "
+                         f"{dt:.2f} s wall"}
+    line = base_line(main["useful_tops"], "TOP/s", args.steps, args.warmup, t, "i8",
+                     "linear convolution: M=8 streams of 10^6 samples U[-2^14,2^14) (int32), "
+                     "shared 4500-tap kernel U[-128,128) (int8); fused entangle + conv + "
+                     "disentangle + check, int32 d_hat",
+                     {"M": M, "samples": nx, "taps": L, "l": ne.ne_params_default(M).l,
+                      "k": ne.ne_params_default(M).k, "w": 64, "digits": digits})
+    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
+                        "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None}
+    line["cpu_baseline"] = cpu
+    line["plain_ms"] = main["plain_ms"]
+    line["overhead_vs_plain_pct"] = main["overhead_vs_plain_pct"]
+    line["corners"] = corners
+    return line
+
+
 def batch_problems(ne, ne_synth, np, torch, dev, recipe):
     probs = []
     useful = issued = 0.0
@@ -547,7 +646,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series"], default="gemm")
+    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series", "linconv"], default="gemm")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -568,7 +667,7 @@ def main():
         traffic_probe(ne, ne_synth, np, torch, dev)
         return
     fn = {"gemm": run_gemm, "conv": run_conv, "batch": run_batch, "stress": run_stress,
-          "series": run_series}
+          "series": run_series, "linconv": run_linconv}
     line = fn[args.workload](args, ne, ne_synth, np, torch, dev)
     print(json.dumps(line), flush=True)
 

@@ -146,6 +146,23 @@ int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64
                     ne_stream_t stream);
 
 /*
+ * Linear convolution of each entangled stream (N samples) with a short
+ * kernel of L taps (section IV: long streams filtered by short kernels,
+ * which the paper processes in overlap-save blocks):
+ *     delta[m][t] = sum_{j=0}^{L-1} eps[m][t - j] * g[j]   (mod 2^64),
+ *     0 <= t < N + L - 1, eps taken as zero outside [0, N).
+ * Every block of 1024 outputs is one Toeplitz x Hankel matrix product over
+ * the L + 32 taps that reach it, on int8 matrix cores (digits as for
+ * ne_lsb_gemm), so the work is proportional to L, not to N.
+ *   eps       device, [M][N] int64; eps_bits as for ne_lsb_gemm.
+ *   g         device, [L] int8.
+ *   delta     device, [M][N + L - 1] int64; must not overlap eps or g.
+ *   N >= 1, 1 <= L <= 131071, N + L - 1 <= 2^30 (else NE_EINVAL).
+ */
+int ne_lsb_linconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t L,
+                   int64_t *delta, int64_t N, const ne_params_t *p, ne_stream_t stream);
+
+/*
  * Workspace bytes that ne_lsb_circconv (fused = 0) or ne_circconv_fused
  * (fused = 1) uses for N taps and M streams; 0 when the taps are not split
  * (then the workspace argument is ignored), and 0 for invalid sizes.
@@ -309,6 +326,24 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
                            int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
                            int64_t N, const ne_params_t *p, void *workspace,
                            int64_t workspace_bytes, ne_stream_t stream);
+
+/*
+ * The linear convolution above fused with entanglement, disentanglement
+ * and the check (the pattern of ne_circconv_fused): c in plain form, the
+ * entangled words formed on load, d_hat = the linear convolution of every
+ * input stream with g, exactly.
+ *   c         device, [M][N] of c_dtype (NE_I8, NE_I32, NE_I64), |c| <
+ *             2^(c_bits-1).
+ *   g         device, [L] int8.
+ *   d_hat     device, [M][N + L - 1] of out_dtype (NE_I32 or NE_I64).
+ *   flags     device, [ceil((N + L - 1) / 32)] uint32, or NULL; n_bad as
+ *             usual.
+ *   Sizes as for ne_lsb_linconv; NE_ERANGE unless L 2^(c_bits-1) 128 <= D.
+ *   One workgroup per block of 1024 outputs; M <= 8.
+ */
+int ne_linconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g, int64_t L,
+                     void *d_hat, int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
+                     int64_t N, const ne_params_t *p, ne_stream_t stream);
 
 /*
  * Workspace bytes of ne_permute_scale_fused: N * ceil(M * c_dtype / 8) * 8;

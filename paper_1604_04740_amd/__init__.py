@@ -108,6 +108,9 @@ def lib():
             "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
                                         _vp, _i64, _vp], ctypes.c_int),
             "ne_permute_workspace": ([_i64, _i32, _i32], _i64),
+            "ne_lsb_linconv": ([_vp, _i32, _vp, _i64, _vp, _i64, P, _vp], ctypes.c_int),
+            "ne_linconv_fused": ([_vp, _i32, _i32, _vp, _i64, _vp, _i32, _vp, _vp, _i64, P, _vp],
+                                 ctypes.c_int),
             "ne_series_range": ([P, _i64, _i32, ctypes.POINTER(_SeriesOp),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64)], ctypes.c_int),
             "ne_series_gemm_scale_permute": ([_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp, _i32, _vp,
@@ -242,6 +245,21 @@ def ne_lsb_circconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params
                               _dev(out, "out", torch.int64), N, ctypes.byref(p), _opt(ws, "ws", None),
                               ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
         "ne_lsb_circconv")
+    return out
+
+
+def ne_lsb_linconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """eps: [M, N] int64, g: [L] int8 -> delta [M, N + L - 1] int64 (linear convolution)."""
+    M, N = eps.shape
+    (L,) = g.shape
+    if M != p.M:
+        raise ValueError("shape mismatch")
+    if out is None:
+        out = torch.empty((M, N + L - 1), dtype=torch.int64, device=eps.device)
+    _ok(lib().ne_lsb_linconv(_dev(eps, "eps", torch.int64), eps_bits, _dev(g, "g", torch.int8), L,
+                             _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
+        "ne_lsb_linconv")
     return out
 
 
@@ -415,6 +433,33 @@ def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
                                 N, ctypes.byref(p), _opt(ws, "ws", None),
                                 ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
         "ne_circconv_fused")
+    return out, flags, n_bad
+
+
+def ne_linconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
+                     out_dtype=torch.int64, out: torch.Tensor | None = None,
+                     flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+    """c: [M, N] int8/int32/int64, g: [L] int8 -> (d_hat [M, N + L - 1],
+    flags [ceil((N + L - 1) / 32)], n_bad)."""
+    M, N = c.shape
+    (L,) = g.shape
+    if M != p.M:
+        raise ValueError("shape mismatch")
+    if c.dtype not in _DT:
+        raise TypeError("c must be int8, int32 or int64")
+    No = N + L - 1
+    if out is None:
+        out = torch.empty((M, No), dtype=out_dtype, device=c.device)
+    if flags is True:
+        flags = torch.empty(((No + 31) // 32,), dtype=torch.int32, device=c.device)
+    elif flags is False:
+        flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    _ok(lib().ne_linconv_fused(_dev(c, "c"), _DT[c.dtype], c_bits, _dev(g, "g", torch.int8), L,
+                               _dev(out, "out", out_dtype), _DT[out_dtype],
+                               _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
+                               N, ctypes.byref(p), _stream()), "ne_linconv_fused")
     return out, flags, n_bad
 
 

@@ -35,6 +35,13 @@ int check_params(const ne_params_t *p, int max_m)
 
 hipStream_t hs(ne_stream_t s) { return (hipStream_t)s; }
 
+// Linear convolution sizes: N >= 1 samples, 1 <= L <= kMaxK taps (exact
+// int32 digit sums), N + L - 1 <= 2^30 outputs per stream.
+bool linconv_sizes_ok(int64_t N, int64_t L)
+{
+    return N >= 1 && L >= 1 && L <= kMaxK && N <= ((int64_t)1 << 30) - L + 1;
+}
+
 } // namespace
 
 extern "C" {
@@ -422,6 +429,55 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
     return launch_permute_scale_fused(c, c_dtype, perm, scale, add, d_hat, out_dtype == NE_I64,
                                       flags, n_bad, N, p->M, p->l, p->r_check, workspace,
                                       hs(stream));
+}
+
+int ne_lsb_linconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t L,
+                   int64_t *delta, int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsElementwise);
+    if (rc)
+        return rc;
+    if (!linconv_sizes_ok(N, L) || eps_bits < 1 || eps_bits > 64)
+        return NE_EINVAL;
+    if (!eps || !g || !delta)
+        return NE_EINVAL;
+    const int64_t ib = N * p->M * 8, ob = (N + L - 1) * p->M * 8;
+    if (overlap(eps, ib, delta, ob) || overlap(g, L, delta, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8)
+        return NE_EALIGN;
+    return launch_linconv_eps(eps, ne::digits_for_bits(eps_bits), g, L, delta, N, p->M,
+                              hs(stream));
+}
+
+int ne_linconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g, int64_t L,
+                     void *d_hat, int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
+                     int64_t N, const ne_params_t *p, ne_stream_t stream)
+{
+    int rc = check_params(p, kMaxStreamsFused);
+    if (rc)
+        return rc;
+    if (!linconv_sizes_ok(N, L) ||
+        (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64) ||
+        (out_dtype != NE_I32 && out_dtype != NE_I64) || c_bits < 1 || c_bits > 8 * c_dtype)
+        return NE_EINVAL;
+    int64_t D = 0;
+    ne_range_bound(p, &D);
+    // a-priori bound L * 2^(c_bits-1) * 128 <= D, compared without overflow
+    if (c_bits - 1 + 7 >= 63 || L > (D >> (c_bits - 1 + 7)))
+        return NE_ERANGE;
+    if (!c || !g || !d_hat)
+        return NE_EINVAL;
+    const int64_t No = N + L - 1;
+    const int64_t ob = No * p->M * out_dtype;
+    if (overlap(c, N * p->M * c_dtype, d_hat, ob) || overlap(g, L, d_hat, ob) ||
+        overlap(flags, ((No + 31) / 32) * 4, d_hat, ob))
+        return NE_EALIAS;
+    if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 ||
+        (uintptr_t)n_bad % 8)
+        return NE_EALIGN;
+    return launch_linconv_fused(c, c_dtype, c_bits, g, L, d_hat, out_dtype == NE_I64, flags, n_bad,
+                                N, p->M, p->l, p->r_check, hs(stream));
 }
 
 int ne_series_range(const ne_params_t *p, int64_t c_max, int32_t n_ops, const ne_series_op_t *ops,

@@ -165,6 +165,8 @@ __device__ __forceinline__ void run_conv_m(const DevProblem &P, int block, int8_
     J.flags = P.flags;
     J.n_bad = P.n_bad;
     J.N = P.N;
+    J.L = P.N;
+    J.Nout = P.N;
     J.M = M;
     J.l = P.l;
     J.r = P.r;

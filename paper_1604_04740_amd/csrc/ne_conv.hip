@@ -77,6 +77,8 @@ int launch_circconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t
     J.out = delta;
     J.out64 = 1;
     J.N = N;
+    J.L = N;
+    J.Nout = N;
     J.M = M;
     const unsigned blocks = (unsigned)((N + kCvBlock - 1) / kCvBlock);
     uint64_t *w = (uint64_t *)ws;
@@ -111,6 +113,8 @@ int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *
     J.flags = flags;
     J.n_bad = n_bad;
     J.N = N;
+    J.L = N;
+    J.Nout = N;
     J.M = M;
     J.l = l;
     J.r = r;
@@ -124,6 +128,70 @@ int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *
     case 8: return launch_fused_m<8>(J, blocks, sp, w, s);
     default: return NE_EUNSUP;
     }
+}
+
+// ---------------------------------------------------- linear convolution
+
+int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t L, int64_t *delta,
+                       int64_t N, int M, hipStream_t s)
+{
+    ConvJob J{};
+    J.x = eps;
+    J.x_dtype = NE_I64;
+    J.digits = digits;
+    J.g = g;
+    J.out = delta;
+    J.out64 = 1;
+    J.N = N;
+    J.L = L;
+    J.Nout = N + L - 1;
+    J.M = M;
+    const unsigned blocks = (unsigned)((J.Nout + kCvBlock - 1) / kCvBlock);
+    const unsigned groups = (unsigned)((M + kCvMaxSlots - 1) / kCvMaxSlots);
+    switch (M) {
+    case 3: k_linconv_staged<3><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+    case 4: k_linconv_staged<4><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+    case 5: k_linconv_staged<5><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+    case 6: k_linconv_staged<6><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+    case 7: k_linconv_staged<7><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+    default:
+        if (M < 3 || M > kMaxStreamsElementwise)
+            return NE_EUNSUP;
+        k_linconv_staged<kCvMaxSlots><<<dim3(blocks, groups), kCvThreads, 0, s>>>(J);
+    }
+    return launch_status();
+}
+
+int launch_linconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, int64_t L,
+                         void *dhat, int out64, uint32_t *flags, unsigned long long *n_bad,
+                         int64_t N, int M, int l, int r, hipStream_t s)
+{
+    ConvJob J{};
+    J.x = c;
+    J.x_dtype = c_dtype;
+    J.digits = cv_digits(c_bits);
+    J.g = g;
+    J.out = dhat;
+    J.out64 = out64;
+    J.flags = flags;
+    J.n_bad = n_bad;
+    J.N = N;
+    J.L = L;
+    J.Nout = N + L - 1;
+    J.M = M;
+    J.l = l;
+    J.r = r;
+    const unsigned blocks = (unsigned)((J.Nout + kCvBlock - 1) / kCvBlock);
+    switch (M) {
+    case 3: k_linconv_fused<3><<<blocks, kCvThreads, 0, s>>>(J); break;
+    case 4: k_linconv_fused<4><<<blocks, kCvThreads, 0, s>>>(J); break;
+    case 5: k_linconv_fused<5><<<blocks, kCvThreads, 0, s>>>(J); break;
+    case 6: k_linconv_fused<6><<<blocks, kCvThreads, 0, s>>>(J); break;
+    case 7: k_linconv_fused<7><<<blocks, kCvThreads, 0, s>>>(J); break;
+    case 8: k_linconv_fused<8><<<blocks, kCvThreads, 0, s>>>(J); break;
+    default: return NE_EUNSUP;
+    }
+    return launch_status();
 }
 
 } // namespace ne

@@ -24,6 +24,14 @@
 // Staged: the sources are given 64-bit words (entangled streams) and delta
 // is written out.
 //
+// Linear convolution (LIN) of a stream of Nx samples with L taps,
+// y[t] = sum_{j<L} x[t - j] g[j] for 0 <= t < Nx + L - 1 (x zero outside):
+// the same block product over i in [0, L + 32) with
+//     A[a][i] = x[t0 + 32 + 32 a - i],   B[i][p] = g[p + i - 32]
+// (zero outside the stream or the kernel); the shift by 32 keeps the tap
+// index of every column non-negative.  Only the taps of the kernel are
+// visited, so the work per block is proportional to L, not to Nx.
+//
 // LDS, per workgroup (4 wavefronts):
 //   A rings   one 2048-byte ring per slot: byte v holds digit d of
 //             x[(t0 - v) mod N], so the 16 bytes a lane needs for row a at
@@ -92,7 +100,9 @@ struct ConvJob {
     int out64;
     uint32_t *flags;            // fused: [ceil(N/32)] or NULL
     unsigned long long *n_bad;  // fused: counter or NULL
-    int64_t N;
+    int64_t N;                  // samples per input stream
+    int64_t L;                  // taps (circular: N)
+    int64_t Nout;               // outputs per stream (circular: N; linear: N + L - 1)
     int M, l, r;
     int s0;                     // staged: first stream of this workgroup
 };
@@ -133,12 +143,16 @@ template <int G>
 struct CvA {
     int64_t val[G];
     int v;
-    __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int idx, int v_)
+    // ok == false: the coordinate lies outside the stream (linear form)
+    __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int idx, int v_,
+                                         bool ok = true)
     {
         v = v_;
 #pragma unroll
         for (int s = 0; s < G; ++s)
-            val[s] = stream[s] >= 0 ? cv_load(J.x, J.x_dtype, (int64_t)stream[s] * J.N + idx) : 0;
+            val[s] = (ok && stream[s] >= 0)
+                         ? cv_load(J.x, J.x_dtype, (int64_t)stream[s] * J.N + idx)
+                         : 0;
     }
     __device__ __forceinline__ void store(int8_t *rings, int d) const
     {
@@ -165,23 +179,33 @@ struct CvG {
     uint32_t w[8];
     int p;
     int i0;
+    template <bool LIN = false>
     __device__ __forceinline__ void load(const ConvJob &J, int I, int tid)
     {
         p = tid >> 3;
         i0 = I + 32 * (tid & 7);
+        if constexpr (LIN) {
+            // B[i][p] = g[p + i - 32], zero outside the L taps
+            const int L = (int)J.L, s = i0 + p - 32;
+            if (s >= 0 && s + 36 <= L) {
+                gather_aligned(J.g + s);
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    uint32_t x = 0;
+                    for (int b = 0; b < 4; ++b) {
+                        const int j = s + 4 * k + b;
+                        const uint32_t byte = (j >= 0 && j < L) ? (uint32_t)(uint8_t)J.g[j] : 0u;
+                        x |= byte << (8 * b);
+                    }
+                    w[k] = x;
+                }
+            }
+            return;
+        }
         const int N = (int)J.N, s = i0 + p;
         if (i0 + 32 <= N && s + 36 <= N) {
-            // g[s .. s+31] from nine aligned dwords inside g
-            const uintptr_t a = (uintptr_t)(J.g + s);
-            const uint32_t *q = (const uint32_t *)(a & ~(uintptr_t)3);
-            const uint32_t sh = (uint32_t)(a & 3);
-            uint32_t u[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                u[k] = q[k];
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], sh);
+            gather_aligned(J.g + s);
         } else {
             // wrap-around or past the last tap: byte by byte
             int j = cv_mod(s, N);
@@ -196,6 +220,21 @@ struct CvG {
                 w[k] = x;
             }
         }
+    }
+    // src[0 .. 31] from nine aligned dwords (all inside the kernel: the
+    // caller checks that src + 36 does not pass its end)
+    __device__ __forceinline__ void gather_aligned(const int8_t *src)
+    {
+        const uintptr_t a = (uintptr_t)src;
+        const uint32_t *q = (const uint32_t *)(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3);
+        uint32_t u[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            u[k] = q[k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], sh);
     }
     __device__ __forceinline__ void store(int8_t *gc) const
     {
@@ -222,7 +261,7 @@ __device__ __forceinline__ void cv_streams(const ConvJob &J, int (&stream)[G])
 // SPLIT (fused only): the own-stream and previous-stream products of every
 // slot are accumulated in two passes of G accumulator sets each instead of
 // one pass of 2G (half the accumulator registers, twice the staging).
-template <int G, bool FUSED, bool SPLIT = false>
+template <int G, bool FUSED, bool SPLIT = false, bool LIN = false>
 __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, int Ia, int Ib,
                                                 const int (&stream)[G], int8_t *lds)
 {
@@ -235,8 +274,9 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int Ni = (int)J.N, t0i = (int)t0, step_mod = kCvStep % Ni;
-    const int Np = (Ni + 31) & ~31;
+    const int Ni = (int)J.N, t0i = (int)t0, step_mod = LIN ? kCvStep : kCvStep % Ni;
+    // taps with a nonzero column of B, rounded to whole k-steps
+    const int Np = LIN ? ((int)J.L + 32 + 31) & ~31 : (Ni + 31) & ~31;
     const int steps = (Ib - Ia) / kCvStep;
     const int a = lane & 31, h = lane >> 5;
 
@@ -274,13 +314,19 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
 #pragma unroll
             for (int u = 0; u < RA; ++u) {
                 const int v = Ia - 992 + k0 + u * kCvThreads + tid;
-                if (k0 + u * kCvThreads + tid < a_bytes)
-                    st[u].load(J, stream, cv_mod(t0i - v, Ni), v);
+                if (k0 + u * kCvThreads + tid < a_bytes) {
+                    if constexpr (LIN) {
+                        const int idx = t0i + 32 - v;
+                        st[u].load(J, stream, idx, v, idx >= 0 && idx < Ni);
+                    } else {
+                        st[u].load(J, stream, cv_mod(t0i - v, Ni), v);
+                    }
+                }
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
                 if (2 * r + u < g_steps)
-                    sg[u].load(J, Ia + (2 * r + u) * kCvStep, tid);
+                    sg[u].template load<LIN>(J, Ia + (2 * r + u) * kCvStep, tid);
 #pragma unroll
             for (int u = 0; u < RA; ++u)
                 if (k0 + u * kCvThreads + tid < a_bytes) {
@@ -296,7 +342,8 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
         }
         // ring coordinate v = Ia + 256 (j + 1) + tid of step j's prefetch,
         // and its input index (t0 - v) mod N, advanced by -256 mod N per step
-        int pidx = cv_mod(t0i - Ia - kCvStep - tid, Ni);
+        // (linear: t0 + 32 - v, advanced by -256, in range or not)
+        int pidx = LIN ? t0i + 32 - Ia - kCvStep - tid : cv_mod(t0i - Ia - kCvStep - tid, Ni);
         __syncthreads();
 
         for (int j = 0; j < steps; ++j) {
@@ -305,10 +352,10 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
             CvA<G> na;
             CvG ng;
             if (more) {
-                na.load(J, stream, pidx, I + kCvStep + tid);
-                ng.load(J, I + kCvStep, tid);
+                na.load(J, stream, pidx, I + kCvStep + tid, !LIN || (pidx >= 0 && pidx < Ni));
+                ng.template load<LIN>(J, I + kCvStep, tid);
                 pidx -= step_mod;
-                if (pidx < 0)
+                if (!LIN && pidx < 0)
                     pidx += Ni;
             }
 #pragma unroll
@@ -377,7 +424,7 @@ __device__ __forceinline__ void conv_finish(const ConvJob &J, const int (&stream
                                             int64_t (&dd)[M])
 {
     const int lane = threadIdx.x & 63;
-    const int64_t N = J.N;
+    const int64_t N = J.Nout;
     const bool valid = t < N;
     int64_t o[M];
     const bool flag = disentangle_rot<M>(dd, J.l, o) && valid;
@@ -405,14 +452,15 @@ __device__ __forceinline__ void conv_finish(const ConvJob &J, const int (&stream
 
 // One whole block of 1024 outputs (all taps) in one workgroup.  FUSED:
 // G == M, disentangle and check; staged: write delta.
-template <int G, bool FUSED, bool SPLIT = false>
+template <int G, bool FUSED, bool SPLIT = false, bool LIN = false>
 __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
 {
     int stream[G];
     cv_streams<G, FUSED>(J, stream);
     const int64_t t0 = block * kCvBlock;
-    const int taps = (int)((J.N + kCvStep - 1) / kCvStep) * kCvStep;
-    conv_accumulate<G, FUSED, SPLIT>(J, t0, 0, taps, stream, lds);
+    const int64_t span = LIN ? J.L + 32 : J.N;
+    const int taps = (int)((span + kCvStep - 1) / kCvStep) * kCvStep;
+    conv_accumulate<G, FUSED, SPLIT, LIN>(J, t0, 0, taps, stream, lds);
     const auto *red = cv_red(lds, G);
     const int tid = threadIdx.x;
 #pragma unroll 1
@@ -425,11 +473,11 @@ __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8
             for (int s = 0; s < G; ++s)
                 dd[s] = (int64_t)red[s * kCvBlock + pos];
             conv_finish<G>(J, stream, t, dd);
-        } else if (t < J.N) {
+        } else if (t < J.Nout) {
 #pragma unroll
             for (int s = 0; s < G; ++s)
                 if (stream[s] >= 0)
-                    ((int64_t *)J.out)[(int64_t)stream[s] * J.N + t] =
+                    ((int64_t *)J.out)[(int64_t)stream[s] * J.Nout + t] =
                         (int64_t)red[s * kCvBlock + pos];
         }
     }
@@ -448,6 +496,23 @@ __global__ __launch_bounds__(kCvThreads) void k_conv_staged(ConvJob J)
     __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
     J.s0 = (int)blockIdx.y * G;
     conv_block<G, false>(J, blockIdx.x, lds);
+}
+
+// Linear convolution, one block of 1024 outputs per workgroup: fused
+// (entangle, convolve, disentangle, check) and staged (delta out).
+template <int M>
+__global__ __launch_bounds__(kCvThreads) void k_linconv_fused(const ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(M)];
+    conv_block<M, true, false, true>(J, blockIdx.x, lds);
+}
+
+template <int G>
+__global__ __launch_bounds__(kCvThreads) void k_linconv_staged(ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
+    J.s0 = (int)blockIdx.y * G;
+    conv_block<G, false, false, true>(J, blockIdx.x, lds);
 }
 
 // Split taps: workgroup (block, z, group) accumulates taps [z KC, (z+1) KC)

@@ -200,3 +200,21 @@ def test_series_argument_errors(ne):
     assert args(1, 0, 64, K, 64, ctypes.c_void_p((1 << 20) + 8), 1 << 30) in (ne.NE_EALIAS,
                                                                               ne.NE_EALIGN)
     assert args(1, 0, 0, K, 64, None, 0) == ne.NE_OK
+
+
+def test_linconv_argument_errors(ne):
+    """Sizes and ranges of the linear convolution are rejected before any
+    launch."""
+    L_ = ne.lib()
+    p = ne.ne_params_default(4)
+    fake = ctypes.c_void_p(1 << 20)
+    fused = lambda N, L, bits: L_.ne_linconv_fused(fake, ne.NE_I32, bits, fake, L, fake,
+                                                   ne.NE_I64, None, None, N, ctypes.byref(p), None)
+    staged = lambda N, L: L_.ne_lsb_linconv(fake, 40, fake, L, fake, N, ctypes.byref(p), None)
+    for N, L in [(0, 5), (5, 0), (-1, 5), (10, 131072), ((1 << 30) - 100, 200)]:
+        assert fused(N, L, 15) == ne.NE_EINVAL, (N, L)
+        assert staged(N, L) == ne.NE_EINVAL, (N, L)
+    assert fused(1000, 100, 33) == ne.NE_EINVAL        # more bits than int32 holds
+    assert fused(1000, 4500, 30) == ne.NE_ERANGE       # 4500 * 2^29 * 128 > D at M = 4
+    assert fused(1000, 100, 15) == ne.NE_EALIAS        # everything at one address
+    assert staged(1000, 100) == ne.NE_EALIAS
