@@ -103,4 +103,51 @@ NE_HD int64_t reentangle(int64_t d, int64_t d_prev, int l)
     return entangle_word(d, d_prev, l);
 }
 
+// ---------------------------------------------------------------------------
+// w = 32 (the word width of the paper's Table II and its experiments): words
+// wrap modulo 2^32 and the disentanglement's 2w-bit interim is a 64-bit
+// integer, so d_temp is formed directly: |d_temp| < 2^((M-2) l + 32) <= 2^62
+// because (M-1) l + k <= 32.  Outputs keep the low 32 bits, and the check
+// rebuilds delta_r from those stored outputs in 64-bit arithmetic:
+//     flag = delta_r != d_hat_r + 2^l d_hat_(r-1)   (64-bit, exact).
+// ---------------------------------------------------------------------------
+NE_HD int32_t entangle_word(int32_t c, int32_t c_prev, int l)
+{
+    return (int32_t)((uint32_t)c + ((uint32_t)c_prev << l));
+}
+
+NE_HD int32_t reentangle(int32_t d, int32_t d_prev, int l)
+{
+    return entangle_word(d, d_prev, l);
+}
+
+template <int M>
+NE_HD bool disentangle_rot(const int32_t (&d)[M], int l, int32_t (&out)[M])
+{
+    const int L = (M - 1) * l;
+    uint64_t t = 0; // d_temp, exact (two's complement in 64 bits)
+#pragma unroll
+    for (int m = 0; m <= M - 2; ++m) {
+        const uint64_t term = (uint64_t)(int64_t)d[1 + m] << ((M - 2 - m) * l);
+        t = (m & 1) ? t - term : t + term;
+    }
+    if (M & 1)
+        t = (uint64_t)0 - t;
+    const int64_t lo = (int64_t)(t << (64 - L)) >> (64 - L);
+    uint64_t diff = t - (uint64_t)lo;
+    if (M & 1)
+        diff = (uint64_t)0 - diff;
+    const int64_t dr = (int64_t)diff >> L;
+    out[0] = (int32_t)dr;
+    out[M - 1] = (int32_t)lo;
+    uint64_t prev = (uint64_t)dr;
+#pragma unroll
+    for (int m = 1; m <= M - 2; ++m) {
+        prev = (uint64_t)(int64_t)d[m] - (prev << l);
+        out[m] = (int32_t)prev;
+    }
+    const uint64_t rebuilt = (uint64_t)(int64_t)out[0] + ((uint64_t)(int64_t)out[M - 1] << l);
+    return (uint64_t)(int64_t)d[0] != rebuilt;
+}
+
 } // namespace ne
