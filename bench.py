@@ -473,6 +473,84 @@ def run_linconv(args, ne, ne_synth, np, torch, dev):
     return line
 
 
+def run_elementwise(args, ne, ne_synth, np, torch, dev):
+    """The staged element-wise path (entangle, permute/scale/add on entangled
+    words, disentangle + check) over M = 4 streams of 2^24 int32 samples, at
+    w = 32 (the paper's word width) and w = 64.  HBM-bound; the line's
+    roofline is the disentangle + check kernel at w = 32."""
+    import oracle
+
+    seed = ne_synth.BASE_SEED + 7
+    Mw, Nw = 4, 1 << 24
+    c = ne_synth.uniform_int(seed, 1, (Mw, Nw), -256, 256).astype(np.int32)
+    log("permutation of 2^24 positions")
+    perm = ne_synth.permutation(seed, 2, Nw).astype(np.int32)
+    s = ne_synth.uniform_int(seed, 3, (Nw,), -3, 4)
+    a = ne_synth.uniform_int(seed, 4, (Nw,), -100, 100)
+    c_d = torch.from_numpy(c).to(dev)
+    perm_d = torch.from_numpy(perm).to(dev)
+    res = {}
+    for w in (32, 64):
+        p = ne.ne_params_default(Mw, w)
+        wt = torch.int32 if w == 32 else torch.int64
+        wb = w // 8
+        s_d = torch.from_numpy(s).to(dev).to(wt)
+        a_d = torch.from_numpy(a).to(dev).to(wt)
+        eps = torch.empty((Mw, Nw), dtype=wt, device=dev)
+        delta = torch.empty_like(eps)
+        dh = torch.empty_like(eps)
+        fl = torch.empty(((Nw + 31) // 32,), dtype=torch.int32, device=dev)
+        nb = torch.zeros((1,), dtype=torch.int64, device=dev)
+        log(f"w = {w}: entangle, permute/scale/add, disentangle + check")
+        t_e = time_launches(lambda: ne.ne_entangle(c_d, p, out=eps), args.steps, args.warmup, torch)
+        t_p = time_launches(lambda: ne.ne_lsb_permute_scale(eps, perm_d, s_d, a_d, p, out=delta),
+                            args.steps, args.warmup, torch)
+        t_c = time_launches(lambda: ne.ne_disentangle_check(delta, p, out=dh, flags=fl, n_bad=nb),
+                            args.steps, args.warmup, torch)
+        assert int(nb.item()) == 0, "clean run flagged positions"
+        got = dh[:, :4096].cpu().numpy().astype(np.int64)
+        want = s[:4096] * c[:, perm[:4096]].astype(np.int64) + a[:4096]
+        assert np.array_equal(got, want), f"w = {w}: outputs differ from the plain result"
+        bytes_e = Mw * Nw * (4 + wb)
+        bytes_c = 2 * Mw * Nw * wb + Nw // 8
+        res[w] = {"entangle_ms": t_e, "permute_scale_ms": t_p, "check_ms": t_c,
+                  "entangle_gbs": bytes_e / (t_e * 1e-3) / 1e9,
+                  "check_gbs": bytes_c / (t_c * 1e-3) / 1e9,
+                  "chain_ms": t_e + t_p + t_c}
+        del eps, delta, dh
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline")
+        S = 1 << 16
+        l32 = oracle.params(Mw, 32)[0]
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.permute_scale_pipeline(c[:, :S].astype(np.int64), np.arange(S),
+                                                s[:S], a[:S], w=32)
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or S >= Nw:
+                break
+            S = min(Nw, max(S * 2, int(S * args.cpu_seconds / max(dt, 1e-3) * 1.1)))
+        assert ref["n_bad"] == 0 and ref["l"] == l32
+        cpu = {"value": S / dt / 1e9, "unit": "Gpos/s", "cores": threads(), "kind": "oracle",
+               "sample": f"the first {S} positions of the {Mw} streams, identity index map, w = 32 "
+                         f"(entangle + scale/add + extract + check); {dt:.2f} s wall"}
+    r32 = res[32]
+    t = r32["chain_ms"]
+    line = base_line(Nw / (t * 1e-3) / 1e9, "Gpos/s", args.steps, args.warmup, t, "i32",
+                     "staged element-wise path at w = 32: M=4 streams of 2^24 int32 samples "
+                     "U[-256,256); entangle, permute/scale U[-3,3]/add U[-100,100) on entangled "
+                     "words with a random permutation, disentangle + check",
+                     {"M": Mw, "N": Nw, "w": 32})
+    line["roofline"] = {"bound": "hbm", "achieved": r32["check_gbs"], "peak": 8000.0,
+                        "unit": "GB/s", "frac": r32["check_gbs"] / 8000.0, "traffic": None,
+                        "kernel": "k_disentangle_check<4, int32>"}
+    line["cpu_baseline"] = cpu
+    line["w32"] = r32
+    line["w64"] = res[64]
+    return line
+
+
 def batch_problems(ne, ne_synth, np, torch, dev, recipe):
     probs = []
     useful = issued = 0.0
@@ -646,7 +724,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series", "linconv"], default="gemm")
+    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series", "linconv", "elementwise"], default="gemm")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -667,7 +745,7 @@ def main():
         traffic_probe(ne, ne_synth, np, torch, dev)
         return
     fn = {"gemm": run_gemm, "conv": run_conv, "batch": run_batch, "stress": run_stress,
-          "series": run_series, "linconv": run_linconv}
+          "series": run_series, "linconv": run_linconv, "elementwise": run_elementwise}
     line = fn[args.workload](args, ne, ne_synth, np, torch, dev)
     print(json.dumps(line), flush=True)
 

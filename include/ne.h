@@ -29,7 +29,14 @@
  *     unsigned long long) is INCREMENTED by the number of flagged positions:
  *     clear it before the first call whose count you want.
  *   - GPU limits: 3 <= M <= 16 for element-wise entry points, 3 <= M <= 8
- *     for the fused GEMM; w must be 64; k >= 1.
+ *     for the fused GEMM; l >= 2.
+ *   - Word width: w = 64 everywhere.  The element-wise entry points
+ *     (ne_entangle, ne_lsb_permute_scale, ne_disentangle_check, ne_recover,
+ *     ne_permute_scale_fused) also take w = 32, the word width of the
+ *     paper's Table II: their word buffers (eps, delta, d_hat, scale, add,
+ *     delta_rebuilt) are then int32, every word operation wraps modulo
+ *     2^32, and the disentanglement's 2w-bit interim is 64-bit.  Other
+ *     entry points return NE_EUNSUP for w != 64.
  */
 #ifndef NE_H
 #define NE_H
@@ -93,14 +100,16 @@ int ne_range_bound(const ne_params_t *p, int64_t *D);
 /*
  * Entanglement, section III-C (the circulant operator E; section III-A for
  * M = 3): for every position n and stream m,
- *     eps[m][n] = c[m][n] + 2^l * c[(m - 1) mod M][n]    (mod 2^64).
- *   c       device, [M][N] elements of type c_dtype (NE_I8, NE_I32, NE_I64).
- *   eps     device, [M][N] int64.  May equal c when c_dtype == NE_I64 (in
- *           place, as the paper stores entangled streams in place of the
- *           inputs); must not otherwise overlap c.
+ *     eps[m][n] = c[m][n] + 2^l * c[(m - 1) mod M][n]    (mod 2^w).
+ *   c       device, [M][N] elements of type c_dtype (NE_I8, NE_I32, NE_I64;
+ *           taken modulo 2^w).
+ *   eps     device, [M][N] words (int64; int32 for w = 32).  May equal c
+ *           when c_dtype is the word type (in place, as the paper stores
+ *           entangled streams in place of the inputs); must not otherwise
+ *           overlap c.
  *   N       elements per stream, >= 0.
  */
-int ne_entangle(const void *c, int32_t c_dtype, int64_t *eps, int64_t N,
+int ne_entangle(const void *c, int32_t c_dtype, void *eps, int64_t N,
                 const ne_params_t *p, ne_stream_t stream);
 
 /*
@@ -173,16 +182,17 @@ int64_t ne_circconv_workspace(int64_t N, int32_t M, int32_t fused);
  * Fixed permutation, scaling and addition on the entangled streams (section
  * II, op in {permutation, x, +}; the constant is self-entangled as the
  * footnote of section III-A requires for + and -):
- *     delta[m][n] = scale[n] * eps[m][perm[n]] + (2^l + 1) * add[n]  (mod 2^64)
+ *     delta[m][n] = scale[n] * eps[m][perm[n]] + (2^l + 1) * add[n]  (mod 2^w)
+ *   eps       device, [M][N] words (int64; int32 for w = 32).
  *   perm      device, [N] int32, a bijection of 0..N-1 (values out of range
  *             are clamped, never read out of bounds).
- *   scale     device, [N] int64, or NULL for 1.
- *   add       device, [N] int64 un-entangled constant, or NULL for 0.
- *   delta     device, [M][N] int64; must not overlap eps.
+ *   scale     device, [N] words, or NULL for 1.
+ *   add       device, [N] words, un-entangled constant, or NULL for 0.
+ *   delta     device, [M][N] words; must not overlap eps.
  */
-int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
-                         const int64_t *add, int64_t *delta, int64_t N,
-                         const ne_params_t *p, ne_stream_t stream);
+int ne_lsb_permute_scale(const void *eps, const int32_t *perm, const void *scale,
+                         const void *add, void *delta, int64_t N, const ne_params_t *p,
+                         ne_stream_t stream);
 
 /*
  * Disentanglement and the post-computation reliability check (section
@@ -195,28 +205,30 @@ int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t 
  *     flag[n] = delta[r][n] != d_hat[r][n] + 2^l d_hat[(r+M-1) mod M][n]  (exact)
  * (the leading (-1)^M and the chain bound m <= M-2 are the readings of the
  * printed formulas that make them exact for every M; for M = 3 they reduce
- * to the special form of section III-A).  d_hat keeps the low 64 bits.
- *   delta     device, [M][N] int64.
- *   d_hat     device, [M][N] int64; may equal delta (in place).
+ * to the special form of section III-A).  d_hat keeps the low w bits; the
+ * check compares the stored d_hat exactly in 2w bits.
+ *   delta     device, [M][N] words (int64; int32 for w = 32).
+ *   d_hat     device, [M][N] words; may equal delta (in place).
  *   flags     device, [ceil(N/32)] uint32 bitmask, or NULL.
  *   n_bad     device counter (incremented), or NULL.
  */
-int ne_disentangle_check(const int64_t *delta, int64_t *d_hat, uint32_t *flags,
+int ne_disentangle_check(const void *delta, void *d_hat, uint32_t *flags,
                          unsigned long long *n_bad, int64_t N, const ne_params_t *p,
                          ne_stream_t stream);
 
 /*
  * Fail-stop recovery (Propositions 1 and 3): every output from the M-1
  * surviving entangled streams, i.e. the disentanglement above with r = lost.
- *   delta          HOST array of M device pointers to the [N] int64 output
- *                  of each stream; delta[lost] is never read (may be NULL).
+ *   delta          HOST array of M device pointers to the [N] word output
+ *                  of each stream (int64; int32 for w = 32); delta[lost] is
+ *                  never read (may be NULL).
  *   lost           0 <= lost < M.
- *   d_hat          device, [M][N] int64; must not overlap any delta[m].
- *   delta_rebuilt  device, [N] int64 or NULL: the lost stream re-created as
- *                  d_hat[lost] + 2^l d_hat[(lost+M-1) mod M] (mod 2^64).
+ *   d_hat          device, [M][N] words; must not overlap any delta[m].
+ *   delta_rebuilt  device, [N] words or NULL: the lost stream re-created as
+ *                  d_hat[lost] + 2^l d_hat[(lost+M-1) mod M] (mod 2^w).
  */
-int ne_recover(const int64_t *const *delta, int32_t lost, int64_t *d_hat,
-               int64_t *delta_rebuilt, int64_t N, const ne_params_t *p, ne_stream_t stream);
+int ne_recover(const void *const *delta, int32_t lost, void *d_hat, void *delta_rebuilt,
+               int64_t N, const ne_params_t *p, ne_stream_t stream);
 
 /*
  * Optional fault injection into the fused GEMM (for measuring detection):
@@ -310,7 +322,8 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
  * checked.  The caller guarantees |scale[n] c + add[n]| <= D (the range of
  * section III-C); it is not checked a priori.
  *   c          device, [M][N] of c_dtype;  perm device [N] int32 (clamped);
- *   scale/add  device [N] int64 or NULL;   d_hat device [M][N] out_dtype;
+ *   scale/add  device [N] words (int64; int32 for w = 32) or NULL;
+ *   d_hat      device [M][N] out_dtype (NE_I32 only for w = 32);
  *   flags      device [ceil(N/32)] or NULL; n_bad device counter or NULL.
  *   workspace  device scratch of ne_permute_workspace(N, M, c_dtype) bytes,
  *              or NULL.  With it a first launch copies the inputs into rows
@@ -322,10 +335,10 @@ int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8
  *              NE_EINVAL.
  */
 int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
-                           const int64_t *scale, const int64_t *add, void *d_hat,
-                           int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                           int64_t N, const ne_params_t *p, void *workspace,
-                           int64_t workspace_bytes, ne_stream_t stream);
+                           const void *scale, const void *add, void *d_hat, int32_t out_dtype,
+                           uint32_t *flags, unsigned long long *n_bad, int64_t N,
+                           const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                           ne_stream_t stream);
 
 /*
  * The linear convolution above fused with entanglement, disentanglement

@@ -166,6 +166,11 @@ def _opt(t, name, dtype):
     return _dev(t, name, dtype) if t is not None else None
 
 
+def _word(p: Params):
+    """torch dtype of the words (eps, delta, d_hat, scale, add) for p.w."""
+    return torch.int32 if p.w == 32 else torch.int64
+
+
 # --------------------------------------------------------------- parameters
 
 def ne_params_default(M: int, w: int = 64) -> Params:
@@ -183,18 +188,19 @@ def ne_range_bound(p: Params) -> int:
 # --------------------------------------------------------------- staged path
 
 def ne_entangle(c: torch.Tensor, p: Params, out: torch.Tensor | None = None) -> torch.Tensor:
-    """c: [M, ...] int8/int32/int64 -> eps [M, ...] int64 (out may be c if int64)."""
+    """c: [M, ...] int8/int32/int64 -> eps [M, ...] words (int64; int32 for
+    p.w == 32; out may be c when c has the word type)."""
     if c.dtype not in _DT:
         raise TypeError("c must be int8, int32 or int64")
     M = c.shape[0]
     if M != p.M:
         raise ValueError("leading dimension must be M")
     if out is None:
-        out = torch.empty(c.shape, dtype=torch.int64, device=c.device)
+        out = torch.empty(c.shape, dtype=_word(p), device=c.device)
     if out.shape != c.shape:
         raise ValueError("out must have the shape of c")
     N = c.numel() // M if M else 0
-    _ok(lib().ne_entangle(_dev(c, "c"), _DT[c.dtype], _dev(out, "out", torch.int64), N,
+    _ok(lib().ne_entangle(_dev(c, "c"), _DT[c.dtype], _dev(out, "out", _word(p)), N,
                           ctypes.byref(p), _stream()), "ne_entangle")
     return out
 
@@ -266,22 +272,25 @@ def ne_lsb_linconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,
 def ne_lsb_permute_scale(eps: torch.Tensor, perm: torch.Tensor, scale: torch.Tensor | None,
                          add: torch.Tensor | None, p: Params,
                          out: torch.Tensor | None = None) -> torch.Tensor:
-    """eps: [M, N] int64; perm [N] int32; scale/add [N] int64 or None."""
+    """eps: [M, N] words; perm [N] int32; scale/add [N] words or None (words:
+    int64, or int32 for p.w == 32)."""
     M, N = eps.shape
     if M != p.M or perm.shape != (N,):
         raise ValueError("shape mismatch")
     if out is None:
         out = torch.empty_like(eps)
-    _ok(lib().ne_lsb_permute_scale(_dev(eps, "eps", torch.int64), _dev(perm, "perm", torch.int32),
-                                   _opt(scale, "scale", torch.int64), _opt(add, "add", torch.int64),
-                                   _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
+    W = _word(p)
+    _ok(lib().ne_lsb_permute_scale(_dev(eps, "eps", W), _dev(perm, "perm", torch.int32),
+                                   _opt(scale, "scale", W), _opt(add, "add", W),
+                                   _dev(out, "out", W), N, ctypes.byref(p), _stream()),
         "ne_lsb_permute_scale")
     return out
 
 
 def ne_disentangle_check(delta: torch.Tensor, p: Params, out: torch.Tensor | None = None,
                          flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
-    """delta: [M, ...] int64 -> (d_hat [M, ...] int64, flags uint32 words or None, n_bad)."""
+    """delta: [M, ...] words -> (d_hat [M, ...] words, flags uint32 words or
+    None, n_bad); words are int64, or int32 for p.w == 32."""
     M = delta.shape[0]
     if M != p.M:
         raise ValueError("leading dimension must be M")
@@ -294,15 +303,15 @@ def ne_disentangle_check(delta: torch.Tensor, p: Params, out: torch.Tensor | Non
         flags = None
     if n_bad is None:
         n_bad = torch.zeros((1,), dtype=torch.int64, device=delta.device)
-    _ok(lib().ne_disentangle_check(_dev(delta, "delta", torch.int64), _dev(out, "out", torch.int64),
+    _ok(lib().ne_disentangle_check(_dev(delta, "delta", _word(p)), _dev(out, "out", _word(p)),
                                    _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
                                    N, ctypes.byref(p), _stream()), "ne_disentangle_check")
     return out, flags, n_bad
 
 
 def ne_recover(deltas, lost: int, p: Params, rebuild: bool = False, out: torch.Tensor | None = None):
-    """deltas: list of M tensors [N] int64 (deltas[lost] may be None).
-    Returns (d_hat [M, N] int64, rebuilt [N] int64 or None)."""
+    """deltas: list of M tensors [N] of words (int64; int32 for p.w == 32;
+    deltas[lost] may be None).  Returns (d_hat [M, N], rebuilt [N] or None)."""
     M = p.M
     if len(deltas) != M:
         raise ValueError("need M stream pointers")
@@ -315,11 +324,11 @@ def ne_recover(deltas, lost: int, p: Params, rebuild: bool = False, out: torch.T
             continue
         if d.numel() != N:
             raise ValueError("every stream must have N words")
-        ptrs[i] = _dev(d, f"deltas[{i}]", torch.int64).value
+        ptrs[i] = _dev(d, f"deltas[{i}]", _word(p)).value
     if out is None:
-        out = torch.empty((M,) + tuple(ref.shape), dtype=torch.int64, device=ref.device)
+        out = torch.empty((M,) + tuple(ref.shape), dtype=_word(p), device=ref.device)
     rb = torch.empty_like(ref) if rebuild else None
-    _ok(lib().ne_recover(ptrs, lost, _dev(out, "out", torch.int64), _opt(rb, "rebuilt", torch.int64),
+    _ok(lib().ne_recover(ptrs, lost, _dev(out, "out", _word(p)), _opt(rb, "rebuilt", _word(p)),
                          N, ctypes.byref(p), _stream()), "ne_recover")
     return out, rb
 
@@ -487,7 +496,7 @@ def ne_permute_scale_fused(c: torch.Tensor, perm: torch.Tensor, scale: torch.Ten
         workspace = torch.empty((need // 8,), dtype=torch.int64, device=c.device)
     ws = workspace if workspace is not None and workspace is not False else None
     _ok(lib().ne_permute_scale_fused(_dev(c, "c"), _DT[c.dtype], _dev(perm, "perm", torch.int32),
-                                     _opt(scale, "scale", torch.int64), _opt(add, "add", torch.int64),
+                                     _opt(scale, "scale", _word(p)), _opt(add, "add", _word(p)),
                                      _dev(out, "out", out_dtype), _DT[out_dtype],
                                      _opt(flags, "flags", torch.int32),
                                      _dev(n_bad, "n_bad", torch.int64), N, ctypes.byref(p),

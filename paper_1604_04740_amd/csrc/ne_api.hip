@@ -20,15 +20,16 @@ bool overlap(const void *a, int64_t abytes, const void *b, int64_t bbytes)
     return a0 < b0 + (uintptr_t)bbytes && b0 < a0 + (uintptr_t)abytes;
 }
 
-// Parameters admissible for the method (section III-C) and built for the GPU.
-int check_params(const ne_params_t *p, int max_m)
+// Parameters admissible for the method (section III-C) and built for the GPU:
+// w = 64, or w = 32 where the entry point has 32-bit word kernels (w32).
+int check_params(const ne_params_t *p, int max_m, bool w32 = false)
 {
     if (!p)
         return NE_EINVAL;
     if (p->M < 3 || p->w < 4 || p->w > 64 || p->l < 2 || p->k < 0 || p->k > p->l ||
         (int64_t)(p->M - 1) * p->l + p->k > p->w || p->r_check < 0 || p->r_check >= p->M)
         return NE_EINVAL;
-    if (p->w != 64 || p->M > max_m)
+    if (!(p->w == 64 || (w32 && p->w == 32)) || p->M > max_m)
         return NE_EUNSUP;
     return NE_OK;
 }
@@ -102,10 +103,10 @@ int ne_range_bound(const ne_params_t *p, int64_t *D)
     return NE_OK;
 }
 
-int ne_entangle(const void *c, int32_t c_dtype, int64_t *eps, int64_t N, const ne_params_t *p,
+int ne_entangle(const void *c, int32_t c_dtype, void *eps, int64_t N, const ne_params_t *p,
                 ne_stream_t stream)
 {
-    int rc = check_params(p, kMaxStreamsElementwise);
+    int rc = check_params(p, kMaxStreamsElementwise, true);
     if (rc)
         return rc;
     if (N < 0 || (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64))
@@ -114,15 +115,16 @@ int ne_entangle(const void *c, int32_t c_dtype, int64_t *eps, int64_t N, const n
         return NE_OK;
     if (!c || !eps)
         return NE_EINVAL;
-    const int64_t cb = N * p->M * c_dtype, eb = N * p->M * 8;
+    const int wb = p->w / 8; // bytes per word
+    const int64_t cb = N * p->M * c_dtype, eb = N * p->M * wb;
     const bool same = (const void *)eps == c;
-    if (same && c_dtype != NE_I64)
+    if (same && c_dtype != wb)
         return NE_EALIAS;
     if (!same && overlap(c, cb, eps, eb))
         return NE_EALIAS;
-    if (((uintptr_t)c % c_dtype) || ((uintptr_t)eps % 8))
+    if (((uintptr_t)c % c_dtype) || ((uintptr_t)eps % wb))
         return NE_EALIGN;
-    return launch_entangle(c, c_dtype, eps, N, p->M, p->l, hs(stream));
+    return launch_entangle(c, c_dtype, eps, N, p->M, p->l, p->w, hs(stream));
 }
 
 int ne_lsb_gemm(const int64_t *eps, int32_t eps_bits, const int8_t *Gt, int64_t *delta,
@@ -195,11 +197,10 @@ int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64
                                need ? workspace : nullptr, hs(stream));
 }
 
-int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
-                         const int64_t *add, int64_t *delta, int64_t N, const ne_params_t *p,
-                         ne_stream_t stream)
+int ne_lsb_permute_scale(const void *eps, const int32_t *perm, const void *scale, const void *add,
+                         void *delta, int64_t N, const ne_params_t *p, ne_stream_t stream)
 {
-    int rc = check_params(p, kMaxStreamsElementwise);
+    int rc = check_params(p, kMaxStreamsElementwise, true);
     if (rc)
         return rc;
     if (N < 0 || N > 0x7fffffff)
@@ -208,21 +209,22 @@ int ne_lsb_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t 
         return NE_OK;
     if (!eps || !perm || !delta)
         return NE_EINVAL;
-    const int64_t bytes = N * p->M * 8;
+    const int wb = p->w / 8;
+    const int64_t bytes = N * p->M * wb;
     if (overlap(eps, bytes, delta, bytes) || overlap(perm, N * 4, delta, bytes) ||
-        overlap(scale, N * 8, delta, bytes) || overlap(add, N * 8, delta, bytes))
+        overlap(scale, N * wb, delta, bytes) || overlap(add, N * wb, delta, bytes))
         return NE_EALIAS;
-    if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8 || (uintptr_t)perm % 4 ||
-        (uintptr_t)scale % 8 || (uintptr_t)add % 8)
+    if ((uintptr_t)eps % wb || (uintptr_t)delta % wb || (uintptr_t)perm % 4 ||
+        (uintptr_t)scale % wb || (uintptr_t)add % wb)
         return NE_EALIGN;
-    return launch_permute_scale(eps, perm, scale, add, delta, N, p->M, p->l, hs(stream));
+    return launch_permute_scale(eps, perm, scale, add, delta, N, p->M, p->l, p->w, hs(stream));
 }
 
-int ne_disentangle_check(const int64_t *delta, int64_t *d_hat, uint32_t *flags,
+int ne_disentangle_check(const void *delta, void *d_hat, uint32_t *flags,
                          unsigned long long *n_bad, int64_t N, const ne_params_t *p,
                          ne_stream_t stream)
 {
-    int rc = check_params(p, kMaxStreamsElementwise);
+    int rc = check_params(p, kMaxStreamsElementwise, true);
     if (rc)
         return rc;
     if (N < 0)
@@ -231,23 +233,24 @@ int ne_disentangle_check(const int64_t *delta, int64_t *d_hat, uint32_t *flags,
         return NE_OK;
     if (!delta || !d_hat)
         return NE_EINVAL;
-    const int64_t bytes = N * p->M * 8;
+    const int wb = p->w / 8;
+    const int64_t bytes = N * p->M * wb;
     if (d_hat != delta && overlap(delta, bytes, d_hat, bytes))
         return NE_EALIAS;
     if (overlap(flags, ((N + 31) / 32) * 4, d_hat, bytes) ||
         overlap(flags, ((N + 31) / 32) * 4, delta, bytes))
         return NE_EALIAS;
-    if ((uintptr_t)delta % 8 || (uintptr_t)d_hat % 8 || (uintptr_t)flags % 4 ||
+    if ((uintptr_t)delta % wb || (uintptr_t)d_hat % wb || (uintptr_t)flags % 4 ||
         (uintptr_t)n_bad % 8)
         return NE_EALIGN;
-    return launch_disentangle_check(delta, d_hat, flags, n_bad, N, p->M, p->l, p->r_check,
+    return launch_disentangle_check(delta, d_hat, flags, n_bad, N, p->M, p->l, p->r_check, p->w,
                                     hs(stream));
 }
 
-int ne_recover(const int64_t *const *delta, int32_t lost, int64_t *d_hat, int64_t *delta_rebuilt,
-               int64_t N, const ne_params_t *p, ne_stream_t stream)
+int ne_recover(const void *const *delta, int32_t lost, void *d_hat, void *delta_rebuilt, int64_t N,
+               const ne_params_t *p, ne_stream_t stream)
 {
-    int rc = check_params(p, kMaxStreamsElementwise);
+    int rc = check_params(p, kMaxStreamsElementwise, true);
     if (rc)
         return rc;
     if (!delta || lost < 0 || lost >= p->M || N < 0)
@@ -257,24 +260,25 @@ int ne_recover(const int64_t *const *delta, int32_t lost, int64_t *d_hat, int64_
     if (!d_hat)
         return NE_EINVAL;
     StreamPtrs sp{};
-    const int64_t out_bytes = N * p->M * 8;
+    const int wb = p->w / 8;
+    const int64_t out_bytes = N * p->M * wb;
     for (int m = 0; m < p->M; ++m) {
         if (m == lost)
             continue;
         if (!delta[m])
             return NE_EINVAL;
-        if (overlap(delta[m], N * 8, d_hat, out_bytes) ||
-            overlap(delta[m], N * 8, delta_rebuilt, N * 8))
+        if (overlap(delta[m], N * wb, d_hat, out_bytes) ||
+            overlap(delta[m], N * wb, delta_rebuilt, N * wb))
             return NE_EALIAS;
-        if ((uintptr_t)delta[m] % 8)
+        if ((uintptr_t)delta[m] % wb)
             return NE_EALIGN;
-        sp.p[m] = delta[m];
+        sp.p[m] = (const int64_t *)delta[m];
     }
-    if (overlap(delta_rebuilt, N * 8, d_hat, out_bytes))
+    if (overlap(delta_rebuilt, N * wb, d_hat, out_bytes))
         return NE_EALIAS;
-    if ((uintptr_t)d_hat % 8 || (uintptr_t)delta_rebuilt % 8)
+    if ((uintptr_t)d_hat % wb || (uintptr_t)delta_rebuilt % wb)
         return NE_EALIGN;
-    return launch_recover(sp, lost, d_hat, delta_rebuilt, N, p->M, p->l, hs(stream));
+    return launch_recover(sp, lost, d_hat, delta_rebuilt, N, p->M, p->l, p->w, hs(stream));
 }
 
 int ne_gemm_fused(const int8_t *c, const int8_t *Gt, void *d_hat, int32_t out_dtype,
@@ -390,44 +394,45 @@ int64_t ne_permute_workspace(int64_t N, int32_t M, int32_t c_dtype)
     return permute_rows_bytes(N, M, c_dtype);
 }
 
-int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
-                           const int64_t *scale, const int64_t *add, void *d_hat,
-                           int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                           int64_t N, const ne_params_t *p, void *workspace,
-                           int64_t workspace_bytes, ne_stream_t stream)
+int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm, const void *scale,
+                           const void *add, void *d_hat, int32_t out_dtype, uint32_t *flags,
+                           unsigned long long *n_bad, int64_t N, const ne_params_t *p,
+                           void *workspace, int64_t workspace_bytes, ne_stream_t stream)
 {
-    int rc = check_params(p, kMaxStreamsElementwise);
+    int rc = check_params(p, kMaxStreamsElementwise, true);
     if (rc)
         return rc;
     if (N < 0 || N > 0x7fffffff || (c_dtype != NE_I8 && c_dtype != NE_I32 && c_dtype != NE_I64) ||
-        (out_dtype != NE_I32 && out_dtype != NE_I64))
+        (out_dtype != NE_I32 && out_dtype != NE_I64) || (p->w == 32 && out_dtype != NE_I32))
         return NE_EINVAL;
     if (N == 0)
         return NE_OK;
     if (!c || !perm || !d_hat)
         return NE_EINVAL;
+    const int wb = p->w / 8;
     const int64_t ob = N * p->M * out_dtype;
     if (overlap(c, N * p->M * c_dtype, d_hat, ob) || overlap(perm, N * 4, d_hat, ob) ||
-        overlap(scale, N * 8, d_hat, ob) || overlap(add, N * 8, d_hat, ob) ||
+        overlap(scale, N * wb, d_hat, ob) || overlap(add, N * wb, d_hat, ob) ||
         overlap(flags, ((N + 31) / 32) * 4, d_hat, ob))
         return NE_EALIAS;
     if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)perm % 4 ||
-        (uintptr_t)scale % 8 || (uintptr_t)add % 8 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
+        (uintptr_t)scale % wb || (uintptr_t)add % wb || (uintptr_t)flags % 4 ||
+        (uintptr_t)n_bad % 8)
         return NE_EALIGN;
     if (workspace) {
         const int64_t need = permute_rows_bytes(N, p->M, c_dtype);
         if (workspace_bytes < need)
             return NE_EINVAL;
         if (overlap(workspace, need, c, N * p->M * c_dtype) || overlap(workspace, need, d_hat, ob) ||
-            overlap(workspace, need, perm, N * 4) || overlap(workspace, need, scale, N * 8) ||
-            overlap(workspace, need, add, N * 8) ||
+            overlap(workspace, need, perm, N * 4) || overlap(workspace, need, scale, N * wb) ||
+            overlap(workspace, need, add, N * wb) ||
             overlap(workspace, need, flags, ((N + 31) / 32) * 4))
             return NE_EALIAS;
         if ((uintptr_t)workspace % 8)
             return NE_EALIGN;
     }
     return launch_permute_scale_fused(c, c_dtype, perm, scale, add, d_hat, out_dtype == NE_I64,
-                                      flags, n_bad, N, p->M, p->l, p->r_check, workspace,
+                                      flags, n_bad, N, p->M, p->l, p->r_check, p->w, workspace,
                                       hs(stream));
 }
 

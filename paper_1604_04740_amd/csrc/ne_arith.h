@@ -111,6 +111,11 @@ NE_HD int64_t reentangle(int64_t d, int64_t d_prev, int l)
 // rebuilds delta_r from those stored outputs in 64-bit arithmetic:
 //     flag = delta_r != d_hat_r + 2^l d_hat_(r-1)   (64-bit, exact).
 // ---------------------------------------------------------------------------
+// Unsigned type of a word, for wrapping arithmetic.
+template <typename W> struct UWord;
+template <> struct UWord<int64_t> { typedef uint64_t type; };
+template <> struct UWord<int32_t> { typedef uint32_t type; };
+
 NE_HD int32_t entangle_word(int32_t c, int32_t c_prev, int l)
 {
     return (int32_t)((uint32_t)c + ((uint32_t)c_prev << l));

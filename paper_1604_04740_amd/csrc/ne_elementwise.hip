@@ -12,18 +12,21 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Words W: int64_t (w = 64) or int32_t (w = 32); every word operation
+// wraps modulo 2^w.
+
 // Section III-C (operator E): eps[m] = c[m] + 2^l c[m-1 mod M].
-// c and eps may be the same buffer (int64 in place): each thread reads all M
-// words of its position before writing any.
-template <int M, typename T>
-__global__ __launch_bounds__(kThreads) void k_entangle(const T *c, int64_t *eps, int64_t N, int l)
+// c and eps may be the same buffer (in place when T is W): each thread reads
+// all M words of its position before writing any.
+template <int M, typename T, typename W>
+__global__ __launch_bounds__(kThreads) void k_entangle(const T *c, W *eps, int64_t N, int l)
 {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += stride) {
-        int64_t v[M];
+        W v[M];
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            v[m] = (int64_t)c[(int64_t)m * N + n];
+            v[m] = (W)c[(int64_t)m * N + n];
 #pragma unroll
         for (int m = 0; m < M; ++m)
             eps[(int64_t)m * N + n] = entangle_word(v[m], v[(m + M - 1) % M], l);
@@ -33,8 +36,8 @@ __global__ __launch_bounds__(kThreads) void k_entangle(const T *c, int64_t *eps,
 // Disentanglement without stream r and the check against stream r.  Each
 // wavefront covers 64 consecutive positions, i.e. whole 32-bit words of the
 // flag mask, so mask words are written without atomics.
-template <int M>
-__global__ __launch_bounds__(kThreads) void k_disentangle_check(const int64_t *delta, int64_t *dhat,
+template <int M, typename W>
+__global__ __launch_bounds__(kThreads) void k_disentangle_check(const W *delta, W *dhat,
                                                                 uint32_t *flags,
                                                                 unsigned long long *n_bad,
                                                                 int64_t N, int l, int r)
@@ -48,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_disentangle_check(const int64_t *d
         const int64_t n = base + lane;
         bool f = false;
         if (n < N) {
-            int64_t d[M], o[M];
+            W d[M], o[M];
 #pragma unroll
             for (int j = 0; j < M; ++j)
                 d[j] = delta[(int64_t)((r + j) % M) * N + n];
@@ -73,17 +76,17 @@ __global__ __launch_bounds__(kThreads) void k_disentangle_check(const int64_t *d
 
 // Fail-stop recovery: the same extraction with r = lost; stream `lost` is
 // never read.  Optionally re-creates the lost entangled stream.
-template <int M>
-__global__ __launch_bounds__(kThreads) void k_recover(StreamPtrs delta, int lost, int64_t *dhat,
-                                                      int64_t *rebuilt, int64_t N, int l)
+template <int M, typename W>
+__global__ __launch_bounds__(kThreads) void k_recover(StreamPtrs delta, int lost, W *dhat,
+                                                      W *rebuilt, int64_t N, int l)
 {
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += stride) {
-        int64_t d[M], o[M];
+        W d[M], o[M];
         d[0] = 0;
 #pragma unroll
         for (int j = 1; j < M; ++j)
-            d[j] = delta.p[(lost + j) % M][n];
+            d[j] = ((const W *)delta.p[(lost + j) % M])[n];
         (void)disentangle_rot<M>(d, l, o);
 #pragma unroll
         for (int j = 0; j < M; ++j)
@@ -93,24 +96,24 @@ __global__ __launch_bounds__(kThreads) void k_recover(StreamPtrs delta, int lost
     }
 }
 
-// delta[m][n] = scale[n] * eps[m][perm[n]] + (2^l + 1) add[n]   (mod 2^64).
-template <int M>
-__global__ __launch_bounds__(kThreads) void k_permute_scale(const int64_t *__restrict__ eps,
+// delta[m][n] = scale[n] * eps[m][perm[n]] + (2^l + 1) add[n]   (mod 2^w).
+template <int M, typename W>
+__global__ __launch_bounds__(kThreads) void k_permute_scale(const W *__restrict__ eps,
                                                             const int32_t *__restrict__ perm,
-                                                            const int64_t *__restrict__ scale,
-                                                            const int64_t *__restrict__ add,
-                                                            int64_t *__restrict__ delta,
-                                                            int64_t N, int l)
+                                                            const W *__restrict__ scale,
+                                                            const W *__restrict__ add,
+                                                            W *__restrict__ delta, int64_t N, int l)
 {
+    typedef typename UWord<W>::type U;
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t n = (int64_t)blockIdx.x * kThreads + threadIdx.x; n < N; n += stride) {
         int64_t src = perm[n];
         src = src < 0 ? 0 : (src >= N ? N - 1 : src);
-        const uint64_t s = scale ? (uint64_t)scale[n] : 1u;
-        const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
+        const U s = scale ? (U)scale[n] : (U)1;
+        const U a = add ? (U)entangle_word(add[n], add[n], l) : (U)0;
 #pragma unroll
         for (int m = 0; m < M; ++m)
-            delta[(int64_t)m * N + n] = (int64_t)(s * (uint64_t)eps[(int64_t)m * N + src] + a);
+            delta[(int64_t)m * N + n] = (W)(s * (U)eps[(int64_t)m * N + src] + a);
     }
 }
 
@@ -137,53 +140,83 @@ int dispatch_m(int M, A... args)
 }
 
 template <int M> struct EntangleL {
-    static int run(const void *c, int dt, int64_t *eps, int64_t N, int l, hipStream_t s)
+    template <typename W>
+    static void go(const void *c, int dt, W *eps, int64_t N, int l, hipStream_t s)
     {
         const unsigned g = grid_for(N, kThreads);
         if (dt == NE_I8)
-            k_entangle<M, int8_t><<<g, kThreads, 0, s>>>((const int8_t *)c, eps, N, l);
+            k_entangle<M, int8_t, W><<<g, kThreads, 0, s>>>((const int8_t *)c, eps, N, l);
         else if (dt == NE_I32)
-            k_entangle<M, int32_t><<<g, kThreads, 0, s>>>((const int32_t *)c, eps, N, l);
+            k_entangle<M, int32_t, W><<<g, kThreads, 0, s>>>((const int32_t *)c, eps, N, l);
         else
-            k_entangle<M, int64_t><<<g, kThreads, 0, s>>>((const int64_t *)c, eps, N, l);
+            k_entangle<M, int64_t, W><<<g, kThreads, 0, s>>>((const int64_t *)c, eps, N, l);
+    }
+    static int run(const void *c, int dt, void *eps, int64_t N, int l, int w, hipStream_t s)
+    {
+        if (w == 32)
+            go<int32_t>(c, dt, (int32_t *)eps, N, l, s);
+        else
+            go<int64_t>(c, dt, (int64_t *)eps, N, l, s);
         return launch_status();
     }
 };
 
 template <int M> struct CheckL {
-    static int run(const int64_t *delta, int64_t *dhat, uint32_t *flags, unsigned long long *nb,
+    template <typename W>
+    static void go(const void *delta, void *dhat, uint32_t *flags, unsigned long long *nb,
                    int64_t N, int l, int r, hipStream_t s)
     {
-        k_disentangle_check<M><<<grid_for(N, kThreads), kThreads, 0, s>>>(delta, dhat, flags, nb,
-                                                                          N, l, r);
+        k_disentangle_check<M, W><<<grid_for(N, kThreads), kThreads, 0, s>>>(
+            (const W *)delta, (W *)dhat, flags, nb, N, l, r);
+    }
+    static int run(const void *delta, void *dhat, uint32_t *flags, unsigned long long *nb,
+                   int64_t N, int l, int r, int w, hipStream_t s)
+    {
+        if (w == 32)
+            go<int32_t>(delta, dhat, flags, nb, N, l, r, s);
+        else
+            go<int64_t>(delta, dhat, flags, nb, N, l, r, s);
         return launch_status();
     }
 };
 
 template <int M> struct RecoverL {
-    static int run(const StreamPtrs *d, int lost, int64_t *dhat, int64_t *rb, int64_t N, int l,
+    static int run(const StreamPtrs *d, int lost, void *dhat, void *rb, int64_t N, int l, int w,
                    hipStream_t s)
     {
-        k_recover<M><<<grid_for(N, kThreads), kThreads, 0, s>>>(*d, lost, dhat, rb, N, l);
+        const unsigned g = grid_for(N, kThreads);
+        if (w == 32)
+            k_recover<M, int32_t><<<g, kThreads, 0, s>>>(*d, lost, (int32_t *)dhat, (int32_t *)rb,
+                                                         N, l);
+        else
+            k_recover<M, int64_t><<<g, kThreads, 0, s>>>(*d, lost, (int64_t *)dhat, (int64_t *)rb,
+                                                         N, l);
         return launch_status();
     }
 };
 
 template <int M> struct PermL {
-    static int run(const int64_t *eps, const int32_t *perm, const int64_t *scale,
-                   const int64_t *add, int64_t *delta, int64_t N, int l, hipStream_t s)
+    static int run(const void *eps, const int32_t *perm, const void *scale, const void *add,
+                   void *delta, int64_t N, int l, int w, hipStream_t s)
     {
-        k_permute_scale<M><<<grid_for(N, kThreads), kThreads, 0, s>>>(eps, perm, scale, add,
-                                                                      delta, N, l);
+        const unsigned g = grid_for(N, kThreads);
+        if (w == 32)
+            k_permute_scale<M, int32_t><<<g, kThreads, 0, s>>>(
+                (const int32_t *)eps, perm, (const int32_t *)scale, (const int32_t *)add,
+                (int32_t *)delta, N, l);
+        else
+            k_permute_scale<M, int64_t><<<g, kThreads, 0, s>>>(
+                (const int64_t *)eps, perm, (const int64_t *)scale, (const int64_t *)add,
+                (int64_t *)delta, N, l);
         return launch_status();
     }
 };
 
 template <int M> struct PermFusedL {
-    template <typename T>
-    static int go(const T *c, uint64_t *rows, const int32_t *perm, const int64_t *scale,
-                  const int64_t *add, void *dhat, int out64, uint32_t *flags,
-                  unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
+    template <typename T, typename W>
+    static int go(const T *c, uint64_t *rows, const int32_t *perm, const W *scale, const W *add,
+                  void *dhat, int out64, uint32_t *flags, unsigned long long *nb, int64_t N, int l,
+                  int r, hipStream_t s)
     {
         const unsigned g = grid_for(N, kThreads);
         if (rows) {
@@ -191,22 +224,33 @@ template <int M> struct PermFusedL {
             if (launch_status())
                 return NE_ELAUNCH;
         }
-        k_permute_scale_fused<M, T><<<g, kThreads, 0, s>>>(c, rows, perm, scale, add, dhat, out64,
-                                                          flags, nb, N, l, r);
+        k_permute_scale_fused<M, T, false, W><<<g, kThreads, 0, s>>>(
+            c, rows, perm, scale, add, dhat, out64, flags, nb, N, l, r);
         return launch_status();
     }
-    static int run(const void *c, int dt, uint64_t *rows, const int32_t *perm,
-                   const int64_t *scale, const int64_t *add, void *dhat, int out64,
-                   uint32_t *flags, unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
+    template <typename W>
+    static int go_w(const void *c, int dt, uint64_t *rows, const int32_t *perm, const void *scale,
+                    const void *add, void *dhat, int out64, uint32_t *flags,
+                    unsigned long long *nb, int64_t N, int l, int r, hipStream_t s)
     {
+        const W *sc = (const W *)scale, *ad = (const W *)add;
         if (dt == NE_I8)
-            return go<int8_t>((const int8_t *)c, rows, perm, scale, add, dhat, out64, flags, nb, N,
-                              l, r, s);
+            return go<int8_t, W>((const int8_t *)c, rows, perm, sc, ad, dhat, out64, flags, nb, N,
+                                 l, r, s);
         if (dt == NE_I32)
-            return go<int32_t>((const int32_t *)c, rows, perm, scale, add, dhat, out64, flags, nb,
-                               N, l, r, s);
-        return go<int64_t>((const int64_t *)c, rows, perm, scale, add, dhat, out64, flags, nb, N,
-                           l, r, s);
+            return go<int32_t, W>((const int32_t *)c, rows, perm, sc, ad, dhat, out64, flags, nb,
+                                  N, l, r, s);
+        return go<int64_t, W>((const int64_t *)c, rows, perm, sc, ad, dhat, out64, flags, nb, N,
+                              l, r, s);
+    }
+    static int run(const void *c, int dt, uint64_t *rows, const int32_t *perm, const void *scale,
+                   const void *add, void *dhat, int out64, uint32_t *flags,
+                   unsigned long long *nb, int64_t N, int l, int r, int w, hipStream_t s)
+    {
+        if (w == 32)
+            return go_w<int32_t>(c, dt, rows, perm, scale, add, dhat, out64, flags, nb, N, l, r,
+                                 s);
+        return go_w<int64_t>(c, dt, rows, perm, scale, add, dhat, out64, flags, nb, N, l, r, s);
     }
 };
 
@@ -217,7 +261,7 @@ template <int M> struct PermRowsL {
                    uint32_t *flags, unsigned long long *nb, int64_t N, int l, int r,
                    hipStream_t s)
     {
-        k_permute_scale_fused<M, int64_t, true><<<grid_for(N, kThreads), kThreads, 0, s>>>(
+        k_permute_scale_fused<M, int64_t, true, int64_t><<<grid_for(N, kThreads), kThreads, 0, s>>>(
             nullptr, (const uint64_t *)rows, perm, nullptr, nullptr, dhat, out64, flags, nb, N, l,
             r);
         return launch_status();
@@ -238,39 +282,38 @@ int64_t permute_rows_bytes(int64_t N, int M, int c_dtype)
     return N * ((M * c_dtype + 7) / 8) * 8;
 }
 
-int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
-                               const int64_t *scale, const int64_t *add, void *dhat, int out64,
-                               uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
-                               int r, void *rows, hipStream_t s)
+int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm, const void *scale,
+                               const void *add, void *dhat, int out64, uint32_t *flags,
+                               unsigned long long *n_bad, int64_t N, int M, int l, int r, int w,
+                               void *rows, hipStream_t s)
 {
     return dispatch_m<PermFusedL>(M, c, c_dtype, (uint64_t *)rows, perm, scale, add, dhat, out64,
-                                  flags, n_bad, N, l, r, s);
+                                  flags, n_bad, N, l, r, w, s);
 }
 
-int launch_entangle(const void *c, int c_dtype, int64_t *eps, int64_t N, int M, int l,
+int launch_entangle(const void *c, int c_dtype, void *eps, int64_t N, int M, int l, int w,
                     hipStream_t s)
 {
-    return dispatch_m<EntangleL>(M, c, c_dtype, eps, N, l, s);
+    return dispatch_m<EntangleL>(M, c, c_dtype, eps, N, l, w, s);
 }
 
-int launch_disentangle_check(const int64_t *delta, int64_t *dhat, uint32_t *flags,
-                             unsigned long long *n_bad, int64_t N, int M, int l, int r,
+int launch_disentangle_check(const void *delta, void *dhat, uint32_t *flags,
+                             unsigned long long *n_bad, int64_t N, int M, int l, int r, int w,
                              hipStream_t s)
 {
-    return dispatch_m<CheckL>(M, delta, dhat, flags, n_bad, N, l, r, s);
+    return dispatch_m<CheckL>(M, delta, dhat, flags, n_bad, N, l, r, w, s);
 }
 
-int launch_recover(const StreamPtrs &delta, int lost, int64_t *dhat, int64_t *rebuilt,
-                   int64_t N, int M, int l, hipStream_t s)
+int launch_recover(const StreamPtrs &delta, int lost, void *dhat, void *rebuilt, int64_t N, int M,
+                   int l, int w, hipStream_t s)
 {
-    return dispatch_m<RecoverL>(M, &delta, lost, dhat, rebuilt, N, l, s);
+    return dispatch_m<RecoverL>(M, &delta, lost, dhat, rebuilt, N, l, w, s);
 }
 
-int launch_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
-                         const int64_t *add, int64_t *delta, int64_t N, int M, int l,
-                         hipStream_t s)
+int launch_permute_scale(const void *eps, const int32_t *perm, const void *scale, const void *add,
+                         void *delta, int64_t N, int M, int l, int w, hipStream_t s)
 {
-    return dispatch_m<PermL>(M, eps, perm, scale, add, delta, N, l, s);
+    return dispatch_m<PermL>(M, eps, perm, scale, add, delta, N, l, w, s);
 }
 
 } // namespace ne

@@ -22,24 +22,25 @@ struct StreamPtrs {
 };
 
 // ---- element-wise kernels (ne_elementwise.hip) ----
-int launch_entangle(const void *c, int c_dtype, int64_t *eps, int64_t N, int M, int l,
+// w = 64: words (eps, delta, d_hat, scale, add) are int64; w = 32: int32.
+int launch_entangle(const void *c, int c_dtype, void *eps, int64_t N, int M, int l, int w,
                     hipStream_t s);
-int launch_disentangle_check(const int64_t *delta, int64_t *dhat, uint32_t *flags,
-                             unsigned long long *n_bad, int64_t N, int M, int l, int r,
+int launch_disentangle_check(const void *delta, void *dhat, uint32_t *flags,
+                             unsigned long long *n_bad, int64_t N, int M, int l, int r, int w,
                              hipStream_t s);
-int launch_recover(const StreamPtrs &delta, int lost, int64_t *dhat, int64_t *rebuilt,
-                   int64_t N, int M, int l, hipStream_t s);
-int launch_permute_scale(const int64_t *eps, const int32_t *perm, const int64_t *scale,
-                         const int64_t *add, int64_t *delta, int64_t N, int M, int l,
-                         hipStream_t s);
+int launch_recover(const StreamPtrs &delta, int lost, void *dhat, void *rebuilt, int64_t N, int M,
+                   int l, int w, hipStream_t s);
+int launch_permute_scale(const void *eps, const int32_t *perm, const void *scale, const void *add,
+                         void *delta, int64_t N, int M, int l, int w, hipStream_t s);
 
 // Bytes of the row copy (M inputs per position, 64-bit padded) that the
 // fused permutation gathers from when given a workspace.
 int64_t permute_rows_bytes(int64_t N, int M, int c_dtype);
-int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm,
-                               const int64_t *scale, const int64_t *add, void *dhat, int out64,
-                               uint32_t *flags, unsigned long long *n_bad, int64_t N, int M, int l,
-                               int r, void *rows, hipStream_t s);
+int launch_permute_scale_fused(const void *c, int c_dtype, const int32_t *perm, const void *scale,
+                               const void *add, void *dhat, int out64, uint32_t *flags,
+                               unsigned long long *n_bad, int64_t N, int M, int l, int r, int w,
+                               void *rows, hipStream_t s);
+
 // Gather of position-major entangled rows [N][M] (no entangle), then
 // disentangle and check.
 int launch_permute_rows_check(const int64_t *rows, const int32_t *perm, void *dhat, int out64,

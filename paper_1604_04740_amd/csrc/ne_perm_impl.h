@@ -51,10 +51,11 @@ __device__ __forceinline__ void perm_pack_range(const T *__restrict__ c,
 // workgroup's 256 threads starting at `first + start`, step `stride`.
 // ENT: the rows already hold entangled 64-bit words (the output of an
 // earlier operation of a series), so the entangle step is skipped.
-template <int M, typename T, bool ENT = false>
+// W: the word (int64_t, w = 64; int32_t, w = 32, then dhat is int32).
+template <int M, typename T, bool ENT = false, typename W = int64_t>
 __device__ __forceinline__ void perm_fused_range(
     const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
-    const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
+    const W *__restrict__ scale, const W *__restrict__ add, void *__restrict__ dhat,
     int out64, uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N,
     int l, int r, int64_t first, int64_t last, int64_t start, int64_t stride)
 {
@@ -119,17 +120,17 @@ __device__ __forceinline__ void perm_fused_range(
             const int64_t n = base + lane;
             bool f = false;
             if (n < last) {
-                const uint64_t sc = scale ? (uint64_t)scale[n] : 1u;
-                const uint64_t a = add ? (uint64_t)entangle_word(add[n], add[n], l) : 0u;
-                int64_t d[M], o[M];
+                typedef typename UWord<W>::type U;
+                const U sc = scale ? (U)scale[n] : (U)1;
+                const U a = add ? (U)entangle_word(add[n], add[n], l) : (U)0;
+                W d[M], o[M];
 #pragma unroll
                 for (int s = 0; s < M; ++s) {
                     if constexpr (ENT)
-                        d[s] = (int64_t)(sc * (uint64_t)v[u][s] + a);
+                        d[s] = (W)(sc * (U)v[u][s] + a);
                     else
-                        d[s] = (int64_t)(sc * (uint64_t)entangle_word(v[u][s],
-                                                                      v[u][(s + M - 1) % M], l) +
-                                         a);
+                        d[s] = (W)(sc * (U)entangle_word((W)v[u][s], (W)v[u][(s + M - 1) % M], l) +
+                                   a);
                 }
                 f = disentangle_rot<M>(d, l, o);
 #pragma unroll
@@ -165,14 +166,14 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_pack(const T *__restrict_
                           (int64_t)gridDim.x * kPermThreads);
 }
 
-template <int M, typename T, bool ENT = false>
+template <int M, typename T, bool ENT = false, typename W = int64_t>
 __global__ __launch_bounds__(kPermThreads) void k_permute_scale_fused(
     const T *__restrict__ c, const uint64_t *__restrict__ rows, const int32_t *__restrict__ perm,
-    const int64_t *__restrict__ scale, const int64_t *__restrict__ add, void *__restrict__ dhat,
+    const W *__restrict__ scale, const W *__restrict__ add, void *__restrict__ dhat,
     int out64, uint32_t *__restrict__ flags, unsigned long long *__restrict__ n_bad, int64_t N,
     int l, int r)
 {
-    perm_fused_range<M, T, ENT>(c, rows, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
+    perm_fused_range<M, T, ENT, W>(c, rows, perm, scale, add, dhat, out64, flags, n_bad, N, l, r, 0, N,
                            (int64_t)blockIdx.x * kPermThreads,
                            (int64_t)gridDim.x * kPermThreads);
 }

@@ -52,10 +52,18 @@ def test_argument_errors_before_launch(ne):
         rc = L.ne_disentangle_check(ctypes.c_void_p(16), ctypes.c_void_p(64), None, None, 10,
                                     ctypes.byref(p), None)
         assert rc == -1, p
-    # valid for the method, not built for the GPU: w = 32
-    p = ne.ne_params_default(3, 32)
+    # valid for the method, not built for the GPU: w = 48, and w = 32 for
+    # the matrix-core entry points; w = 32 is accepted element-wise
+    p = ne.ne_params_default(3, 48)
     rc = L.ne_disentangle_check(ctypes.c_void_p(16), ctypes.c_void_p(64), None, None, 10,
                                 ctypes.byref(p), None)
+    assert rc == -5
+    p = ne.ne_params_default(3, 32)
+    rc = L.ne_disentangle_check(ctypes.c_void_p(16), ctypes.c_void_p(4096), ctypes.c_void_p(16),
+                                None, 10, ctypes.byref(p), None)
+    assert rc == -3  # accepted, then rejected for the flags overlap, before any launch
+    rc = L.ne_lsb_gemm(ctypes.c_void_p(16), 8, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 4,
+                       16, 4, ctypes.byref(p), None)
     assert rc == -5
     p = ne.ne_params_default(3)
     # overlapping delta / d_hat (not identical)
