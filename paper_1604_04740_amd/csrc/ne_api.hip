@@ -498,7 +498,7 @@ int ne_series_range(const ne_params_t *p, int64_t c_max, int32_t n_ops, const ne
     // Bounds are exact integers, saturated at 2^126 (far above any D).
     typedef unsigned __int128 u128;
     const u128 cap = (u128)1 << 126;
-    auto mul = [cap](u128 a, u128 b) -> u128 {
+    auto mul = [](u128 a, u128 b) -> u128 {
         if (a == 0 || b == 0)
             return 0;
         return a > cap / b ? cap : a * b;

@@ -107,15 +107,6 @@ struct ConvJob {
     int s0;                     // staged: first stream of this workgroup
 };
 
-__device__ __forceinline__ int64_t cv_load(const void *x, int dt, int64_t i)
-{
-    if (dt == NE_I8)
-        return ((const int8_t *)x)[i];
-    if (dt == NE_I32)
-        return ((const int32_t *)x)[i];
-    return ((const int64_t *)x)[i];
-}
-
 __device__ __forceinline__ int8_t cv_digit(int64_t v, int d)
 {
     int8_t e = digit(v);
@@ -139,35 +130,71 @@ __device__ __forceinline__ int cv_mod(int a, int N)
 }
 
 // One thread's share of an A-ring step: ring coordinate v of every slot.
+// The samples are kept as loaded (int8 and int32 sign-extended in lo,
+// int64 in hi:lo) and widened only when stored: an instruction that uses a
+// load's result right after it makes the wavefront wait for that load
+// alone, so the loads of a step would be served one after another.
 template <int G>
 struct CvA {
-    int64_t val[G];
+    uint32_t lo[G], hi[G];
+    uint32_t valid; // bit s: slot s holds a sample (else it counts as 0)
     int v;
-    // ok == false: the coordinate lies outside the stream (linear form)
+    // ok == false: the coordinate lies outside the stream (linear form).
+    // Every lane loads (from index 0 where it has no sample) and the dtype
+    // test is uniform, so no load result is overwritten while in flight.
     __device__ __forceinline__ void load(const ConvJob &J, const int (&stream)[G], int idx, int v_,
                                          bool ok = true)
     {
         v = v_;
+        const int ic = ok ? idx : 0;
+        valid = 0;
 #pragma unroll
         for (int s = 0; s < G; ++s)
-            val[s] = (ok && stream[s] >= 0)
-                         ? cv_load(J.x, J.x_dtype, (int64_t)stream[s] * J.N + idx)
-                         : 0;
+            if (ok && stream[s] >= 0)
+                valid |= 1u << s;
+        if (J.x_dtype == NE_I64) {
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                const int64_t i = (int64_t)(stream[s] < 0 ? 0 : stream[s]) * J.N + ic;
+                const uint2 w = ((const uint2 *)J.x)[i];
+                lo[s] = w.x;
+                hi[s] = w.y;
+            }
+        } else if (J.x_dtype == NE_I32) {
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                lo[s] = ((const uint32_t *)J.x)[(int64_t)(stream[s] < 0 ? 0 : stream[s]) * J.N + ic];
+                hi[s] = 0;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                lo[s] = (uint32_t)(int32_t)(
+                    (const int8_t *)J.x)[(int64_t)(stream[s] < 0 ? 0 : stream[s]) * J.N + ic];
+                hi[s] = 0;
+            }
+        }
     }
-    __device__ __forceinline__ void store(int8_t *rings, int d) const
+    __device__ __forceinline__ int64_t value(int s, int dt) const
+    {
+        const int64_t x =
+            dt == NE_I64 ? (int64_t)(((uint64_t)hi[s] << 32) | lo[s]) : (int64_t)(int32_t)lo[s];
+        return (valid >> s) & 1 ? x : 0;
+    }
+    __device__ __forceinline__ void store(int8_t *rings, int d, int dt) const
     {
         const int off = cv_ring_off(v);
 #pragma unroll
         for (int s = 0; s < G; ++s)
-            rings[s * kCvRing + off] = cv_digit(val[s], d);
+            rings[s * kCvRing + off] = cv_digit(value(s, dt), d);
     }
     // every digit: digit dd of slot s into ring s + G dd
-    __device__ __forceinline__ void store_all(int8_t *rings, int digits) const
+    __device__ __forceinline__ void store_all(int8_t *rings, int digits, int dt) const
     {
         const int off = cv_ring_off(v);
 #pragma unroll
         for (int s = 0; s < G; ++s) {
-            int64_t x = val[s];
+            int64_t x = value(s, dt);
             for (int dd = 0; dd < digits; ++dd)
                 rings[(s + G * dd) * kCvRing + off] = digit(x);
         }
@@ -175,8 +202,11 @@ struct CvA {
 };
 
 // One thread's share of a g-copy step: 32 taps [i0, i0 + 32) of copy p.
+// w holds nine dwords and sh a byte shift; tap word k is
+// alignbyte(w[k + 1], w[k], sh), formed only when stored (as for CvA).
 struct CvG {
-    uint32_t w[8];
+    uint32_t w[9];
+    uint32_t sh;
     int p;
     int i0;
     template <bool LIN = false>
@@ -184,19 +214,29 @@ struct CvG {
     {
         p = tid >> 3;
         i0 = I + 32 * (tid & 7);
+        sh = 0;
+        w[8] = 0;
         if constexpr (LIN) {
             // B[i][p] = g[p + i - 32], zero outside the L taps
             const int L = (int)J.L, s = i0 + p - 32;
             if (s >= 0 && s + 36 <= L) {
                 gather_aligned(J.g + s);
             } else {
+                // byte by byte; every byte load is issued (from tap 0 where
+                // there is no tap) before any is used
+                uint32_t b[32];
+#pragma unroll
+                for (int q = 0; q < 32; ++q) {
+                    const int j = s + q;
+                    b[q] = (uint32_t)(uint8_t)J.g[(j >= 0 && j < L) ? j : 0];
+                }
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     uint32_t x = 0;
-                    for (int b = 0; b < 4; ++b) {
-                        const int j = s + 4 * k + b;
-                        const uint32_t byte = (j >= 0 && j < L) ? (uint32_t)(uint8_t)J.g[j] : 0u;
-                        x |= byte << (8 * b);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int j = s + 4 * k + q;
+                        x |= ((j >= 0 && j < L) ? b[4 * k + q] : 0u) << (8 * q);
                     }
                     w[k] = x;
                 }
@@ -207,40 +247,45 @@ struct CvG {
         if (i0 + 32 <= N && s + 36 <= N) {
             gather_aligned(J.g + s);
         } else {
-            // wrap-around or past the last tap: byte by byte
+            // wrap-around or past the last tap: byte by byte, every load
+            // issued before any is used
+            uint32_t b[32];
             int j = cv_mod(s, N);
+#pragma unroll
+            for (int q = 0; q < 32; ++q) {
+                b[q] = (uint32_t)(uint8_t)J.g[j];
+                j = j + 1 == N ? 0 : j + 1;
+            }
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 uint32_t x = 0;
-                for (int b = 0; b < 4; ++b) {
-                    const uint32_t byte = i0 + 4 * k + b < N ? (uint32_t)(uint8_t)J.g[j] : 0u;
-                    x |= byte << (8 * b);
-                    j = j + 1 == N ? 0 : j + 1;
-                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    x |= (i0 + 4 * k + q < N ? b[4 * k + q] : 0u) << (8 * q);
                 w[k] = x;
             }
         }
     }
-    // src[0 .. 31] from nine aligned dwords (all inside the kernel: the
-    // caller checks that src + 36 does not pass its end)
+    // src[0 .. 31] as nine aligned dwords and a shift (all inside the
+    // kernel: the caller checks that src + 36 does not pass its end)
     __device__ __forceinline__ void gather_aligned(const int8_t *src)
     {
         const uintptr_t a = (uintptr_t)src;
         const uint32_t *q = (const uint32_t *)(a & ~(uintptr_t)3);
-        const uint32_t sh = (uint32_t)(a & 3);
-        uint32_t u[9];
+        sh = (uint32_t)(a & 3);
 #pragma unroll
         for (int k = 0; k < 9; ++k)
-            u[k] = q[k];
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            w[k] = __builtin_amdgcn_alignbyte(u[k + 1], u[k], sh);
+            w[k] = q[k];
     }
     __device__ __forceinline__ void store(int8_t *gc) const
     {
         int8_t *dst = gc + p * kCvGStride + (int)(i0 & (kCvGRing - 1));
-        *(cv4i *)dst = cv4i{(int)w[0], (int)w[1], (int)w[2], (int)w[3]};
-        *(cv4i *)(dst + 16) = cv4i{(int)w[4], (int)w[5], (int)w[6], (int)w[7]};
+        uint32_t t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            t[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
+        *(cv4i *)dst = cv4i{(int)t[0], (int)t[1], (int)t[2], (int)t[3]};
+        *(cv4i *)(dst + 16) = cv4i{(int)t[4], (int)t[5], (int)t[6], (int)t[7]};
     }
 };
 
@@ -331,9 +376,9 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
             for (int u = 0; u < RA; ++u)
                 if (k0 + u * kCvThreads + tid < a_bytes) {
                     if (alld)
-                        st[u].store_all(rings, J.digits);
+                        st[u].store_all(rings, J.digits, J.x_dtype);
                     else
-                        st[u].store(rings, d);
+                        st[u].store(rings, d, J.x_dtype);
                 }
 #pragma unroll
             for (int u = 0; u < 2; ++u)
@@ -385,7 +430,7 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
                 }
             }
             if (more) {
-                na.store(rings, d);
+                na.store(rings, d, J.x_dtype);
                 ng.store(gc);
             }
             if (!oneshot)
