@@ -828,6 +828,16 @@ struct SeriesV : FusedV<M> {
 #pragma unroll
         for (int j = 0; j < CB; ++j) {
             const int64_t col = col0 + (wn * CB + j) * 32 + acc_col(lane);
+            // the scale and add words of the lane's 16 positions, all loaded
+            // before the first is used (from position 0 where there is none)
+            uint64_t sc[16], ad[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * 32 + acc_row(r, lane);
+                const int64_t q = (row < g.n && col < g.N) ? row * g.N + col : 0;
+                sc[r] = g.scale ? (uint64_t)g.scale[q] : 1u;
+                ad[r] = g.add ? (uint64_t)g.add[q] : 0u;
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t row = row0 + wm * 32 + acc_row(r, lane);
@@ -841,11 +851,10 @@ struct SeriesV : FusedV<M> {
                 }
                 if (row < g.n && col < g.N) {
                     const int64_t q = row * g.N + col;
-                    const uint64_t sc = g.scale ? (uint64_t)g.scale[q] : 1u;
-                    const uint64_t a = g.add ? (uint64_t)entangle_word(g.add[q], g.add[q], g.l) : 0u;
+                    const uint64_t a = (uint64_t)entangle_word((int64_t)ad[r], (int64_t)ad[r], g.l);
 #pragma unroll
                     for (int s = 0; s < M; ++s)
-                        g.rows[q * M + s] = (int64_t)(sc * d[s] + a);
+                        g.rows[q * M + s] = (int64_t)(sc[r] * d[s] + a);
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
