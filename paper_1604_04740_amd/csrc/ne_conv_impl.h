@@ -184,9 +184,22 @@ struct CvA {
     __device__ __forceinline__ void store(int8_t *rings, int d, int dt) const
     {
         const int off = cv_ring_off(v);
+        if (dt == NE_I64) {
 #pragma unroll
-        for (int s = 0; s < G; ++s)
-            rings[s * kCvRing + off] = cv_digit(value(s, dt), d);
+            for (int s = 0; s < G; ++s)
+                rings[s * kCvRing + off] = cv_digit(value(s, dt), d);
+        } else {
+            // samples of at most 32 bits: the same balanced digits in 32-bit
+            // arithmetic; (x - e) / 256 = floor(x / 256) + bit 7 of x, which
+            // cannot overflow
+#pragma unroll
+            for (int s = 0; s < G; ++s) {
+                int32_t x = (valid >> s) & 1 ? (int32_t)lo[s] : 0;
+                for (int j = 0; j < d; ++j)
+                    x = (x >> 8) + ((x >> 7) & 1);
+                rings[s * kCvRing + off] = (int8_t)(x & 0xFF);
+            }
+        }
     }
     // every digit: digit dd of slot s into ring s + G dd
     __device__ __forceinline__ void store_all(int8_t *rings, int digits, int dt) const

@@ -125,3 +125,18 @@ def test_linconv_range_rejected(ne):
     with pytest.raises(ne.NEError) as e:
         ne.ne_linconv_fused(c, g, p, c_bits=24)
     assert e.value.code == ne.NE_ERANGE
+
+
+def test_linconv_fused_int32_extremes(ne, orc):
+    """Full-width int32 samples (c_bits = 32: five balanced digits), the
+    extreme values included."""
+    M, nx, L = 8, 3000, 7
+    c = ne_synth.uniform_int(2850, 1, (M, nx), -(1 << 31), 1 << 31)
+    c[:, :4] = [(1 << 31) - 1, -(1 << 31), -1, 0]
+    g = ne_synth.uniform_int(2850, 2, (L,), -128, 128).astype(np.int8)
+    g[:2] = [-128, 127]
+    p = ne.ne_params_default(M)
+    ref = orc.linconv_pipeline(c, g.astype(np.int64))
+    dh, fl, nb = ne.ne_linconv_fused(_t(c.astype(np.int32)), _t(g), p, c_bits=32)
+    assert np.array_equal(_h(dh), ref["dhat"])
+    assert int(nb.item()) == 0 and not _bits(_h(fl), nx + L - 1).any()
