@@ -276,17 +276,26 @@ int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, i
                      int64_t N, ne_stream_t stream);
 
 /*
- * Baseline: checksum-stream ABFT of section II-A for the same GEMM, one
- * launch.  The checksum stream r = sum_m c[m] is built in the prologue
- * (two signed int8 digits, since |r| <= 128 M), multiplied by G alongside
- * the M streams, and the epilogue flags positions where
- * sum_m d[m] != e (section II-A).
+ * Baseline: checksum-stream ABFT of section II-A for the same GEMM.  The
+ * checksum stream r = sum_m c[m] (two signed int8 digits, since
+ * |r| <= 128 M) is multiplied by G alongside the M streams, and the epilogue
+ * flags positions where sum_m d[m] != e (section II-A).
  *   c  device [M][n][K] int8;  Gt device [N][K] int8;
  *   d  device [M][n][N] int32;  flags row-padded as for ne_gemm_fused.
+ *   workspace  device, ne_abft_workspace(n, K) bytes (16-byte aligned, no
+ *              overlap with the other arguments), or NULL.  With it a first
+ *              launch writes the checksum stream as two int8 digit planes
+ *              and the GEMM runs every source through the DMA pipeline of
+ *              the fused path (K % 16 == 0 and 16-byte aligned c and Gt;
+ *              otherwise the workspace is not used); with NULL one launch
+ *              builds the checksum while staging its operands.
  */
 int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *flags,
                     unsigned long long *n_bad, int32_t M, int64_t n, int64_t K, int64_t N,
-                    ne_stream_t stream);
+                    void *workspace, int64_t workspace_bytes, ne_stream_t stream);
+
+/* Workspace bytes of ne_abft_gemm_i8: 2 n K (0 for invalid sizes). */
+int64_t ne_abft_workspace(int64_t n, int64_t K);
 
 /*
  * Fused circular convolution, one launch: the star operator of section II on

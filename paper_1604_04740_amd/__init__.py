@@ -20,6 +20,7 @@ __all__ = [
     "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
+    "ne_abft_workspace",
     "ne_circconv_fused", "ne_circconv_workspace", "ne_permute_scale_fused", "ne_permute_workspace", "Inject", "Problem", "Batch", "ne_batch_plan",
     "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
@@ -101,7 +102,8 @@ def lib():
             "ne_gemm_fused": ([_vp, _vp, _vp, _i32, _vp, _vp, _i64, _i64, _i64, P,
                                ctypes.POINTER(_Inject), _vp], ctypes.c_int),
             "ne_plain_gemm_i8": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp], ctypes.c_int),
-            "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp],
+            "ne_abft_workspace": ([_i64, _i64], _i64),
+            "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp],
                                 ctypes.c_int),
             "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp,
                                    _i64, _vp], ctypes.c_int),
@@ -392,9 +394,16 @@ def ne_plain_gemm_i8(A: torch.Tensor, Bt: torch.Tensor, out: torch.Tensor | None
     return out
 
 
+def ne_abft_workspace(n: int, K: int) -> int:
+    return int(lib().ne_abft_workspace(n, K))
+
+
 def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None = None,
-                    flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
-    """c: [M, n, K] int8, Gt: [N, K] int8 -> (d [M, n, N] int32, flags, n_bad)."""
+                    flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None,
+                    workspace=True):
+    """c: [M, n, K] int8, Gt: [N, K] int8 -> (d [M, n, N] int32, flags, n_bad).
+    workspace=True allocates the checksum planes (DMA pipeline); None: the
+    single-launch form; or a caller tensor of ne_abft_workspace(n, K) bytes."""
     M, n, K = c.shape
     N, K2 = Gt.shape
     if K2 != K:
@@ -407,9 +416,15 @@ def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None 
         flags = None
     if n_bad is None:
         n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    if workspace is True:
+        need = int(lib().ne_abft_workspace(n, K))
+        workspace = torch.empty((max(need, 16) // 8 + 2,), dtype=torch.int64, device=c.device)
+    ws = workspace if workspace is not None and workspace is not False else None
     _ok(lib().ne_abft_gemm_i8(_dev(c, "c", torch.int8), _dev(Gt, "Gt", torch.int8),
                               _dev(out, "out", torch.int32), _opt(flags, "flags", torch.int32),
-                              _dev(n_bad, "n_bad", torch.int64), M, n, K, N, _stream()),
+                              _dev(n_bad, "n_bad", torch.int64), M, n, K, N,
+                              _opt(ws, "workspace", None),
+                              ws.numel() * ws.element_size() if ws is not None else 0, _stream()),
         "ne_abft_gemm_i8")
     return out, flags, n_bad
 

@@ -328,9 +328,16 @@ int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, i
     return launch_gemm_plain(A, Bt, C, R, K, N, hs(stream));
 }
 
+int64_t ne_abft_workspace(int64_t n, int64_t K)
+{
+    if (n < 0 || K < 0 || (K > 0 && n > INT64_MAX / 2 / K))
+        return 0;
+    return 2 * n * K;
+}
+
 int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *flags,
                     unsigned long long *n_bad, int32_t M, int64_t n, int64_t K, int64_t N,
-                    ne_stream_t stream)
+                    void *workspace, int64_t workspace_bytes, ne_stream_t stream)
 {
     if (M < 1 || M > kMaxStreamsFused || n < 0 || K < 0 || N < 0 || K > kMaxK)
         return NE_EINVAL;
@@ -344,7 +351,18 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
         return NE_EALIAS;
     if ((uintptr_t)d % 4 || (uintptr_t)flags % 4 || (uintptr_t)n_bad % 8)
         return NE_EALIGN;
-    return launch_gemm_abft(c, Gt, d, flags, n_bad, n, K, N, M, hs(stream));
+    if (workspace) {
+        const int64_t need = ne_abft_workspace(n, K);
+        if (workspace_bytes < need)
+            return NE_EINVAL;
+        if (overlap(workspace, need, c, (int64_t)M * n * K) || overlap(workspace, need, Gt, N * K) ||
+            overlap(workspace, need, d, ob) ||
+            overlap(workspace, need, flags, n * ((N + 31) / 32) * 4))
+            return NE_EALIAS;
+        if ((uintptr_t)workspace % 16)
+            return NE_EALIGN;
+    }
+    return launch_gemm_abft(c, Gt, d, flags, n_bad, n, K, N, M, workspace, hs(stream));
 }
 
 int ne_circconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g,

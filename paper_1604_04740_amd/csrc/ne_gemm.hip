@@ -178,10 +178,57 @@ int launch_series_gemm(const int8_t *c, const int8_t *Bt, const int64_t *scale, 
     }
 }
 
+template <int M>
+int launch_abft_dma_m(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
+                      unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int8_t *planes,
+                      hipStream_t s)
+{
+    using V = AbftDmaV<M>;
+    const int64_t count = n * K;
+    int8_t *lo = planes, *hi = planes + count;
+    const int64_t blocks = (count / 16 + kThreads - 1) / kThreads;
+    k_abft_checksum<M><<<(unsigned)(blocks < 8192 ? (blocks < 1 ? 1 : blocks) : 8192), kThreads, 0,
+                         s>>>(c, lo, hi, count);
+    if (launch_status())
+        return NE_ELAUNCH;
+    typename V::Args a{};
+    a.Bt = Bt;
+    a.K = K;
+    a.N = N;
+    a.c = c;
+    a.rlo = lo;
+    a.rhi = hi;
+    a.d = d;
+    a.flags = flags;
+    a.n_bad = n_bad;
+    a.n = n;
+    const int64_t tm = (n + V::BMS - 1) / V::BMS, tn = (N + V::BN - 1) / V::BN;
+    if (tm * tn > 0x7fffffff)
+        return NE_EINVAL;
+    a.tiles_m = (int)tm;
+    a.tiles_n = (int)tn;
+    k_gemm_dma<V, V::kBK, V::kStages><<<dim3((unsigned)(tm * tn)), kThreads, 0, s>>>(a);
+    return launch_status();
+}
+
 int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
                      unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M,
-                     hipStream_t s)
+                     void *ws, hipStream_t s)
 {
+    if (ws && K > 0 && K % 16 == 0 && aligned16(c) && aligned16(Bt)) {
+        int8_t *pl = (int8_t *)ws;
+        switch (M) {
+        case 1: return launch_abft_dma_m<1>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 2: return launch_abft_dma_m<2>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 3: return launch_abft_dma_m<3>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 4: return launch_abft_dma_m<4>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 5: return launch_abft_dma_m<5>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 6: return launch_abft_dma_m<6>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 7: return launch_abft_dma_m<7>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        case 8: return launch_abft_dma_m<8>(c, Bt, d, flags, n_bad, n, K, N, pl, s);
+        default: return NE_EUNSUP;
+        }
+    }
     switch (M) {
     case 1: return launch_abft_m<1>(c, Bt, d, flags, n_bad, n, K, N, s);
     case 2: return launch_abft_m<2>(c, Bt, d, flags, n_bad, n, K, N, s);

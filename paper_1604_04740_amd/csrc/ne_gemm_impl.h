@@ -1,7 +1,7 @@
 // ne_gemm_impl.h -- int8 matrix-core GEMM device code for gfx950 (shared by
 // the GEMM entry points and the batched persistent kernel).
 //
-// One kernel template, five variants:
+// One kernel template, six variants:
 //   PlainV     C = A * B, int8 -> int32 (the fault-intolerant baseline)
 //   EpsV<L>    delta = eps * G on generic int64 words: each word is split
 //              into L signed int8 digits in the prologue, one exact int32
@@ -16,6 +16,9 @@
 //              FusedV's prologue and products, then scale and add on the
 //              entangled words in the epilogue, stored position-major for
 //              the operation that follows; no disentangle
+//   AbftDmaV<M> the same ABFT with the checksum stream built beforehand as
+//              two int8 digit planes, so every source goes through the DMA
+//              pipeline of FusedV
 //   AbftV<M>   checksum-stream ABFT of section II-A: the checksum row
 //              sum_m c_m (two int8 digits) is built in the prologue and
 //              multiplied alongside the M streams; the epilogue checks
@@ -950,6 +953,111 @@ struct AbftV {
             atomicAdd(g.n_bad, cnt);
     }
 };
+
+// Checksum-stream ABFT through the DMA pipeline: the checksum stream
+// r = sum_m c_m is built beforehand (k_abft_checksum) as two int8 digit
+// planes, so that all M + 2 sources are plain int8 rows the DMA engine
+// copies into LDS; one accumulator set per source.
+template <int M>
+struct AbftDmaV {
+    static constexpr int NSRC = M + 2, P = M + 2, BMS = 32, BN = (M <= 4) ? 256 : 128, WM = 1,
+                         WN = 4;
+    static constexpr int kOcc = 1;
+    static constexpr bool kDma = true;
+    static constexpr int kBK = 128, kStages = 2;
+    static constexpr int RB = 1, CB = BN / 128;
+    __host__ __device__ static constexpr int src(int p) { return p; }
+    struct Args : ArgsBase {
+        const int8_t *c;
+        const int8_t *rlo, *rhi; // checksum digit planes [n][K]
+        int32_t *d;
+        uint32_t *flags;
+        unsigned long long *n_bad;
+        int64_t n;
+    };
+    __device__ __forceinline__ static const int8_t *source_base(const Args &g, int s, int64_t row0)
+    {
+        if (s < M)
+            return g.c + ((int64_t)s * g.n + row0) * g.K;
+        return (s == M ? g.rlo : g.rhi) + row0 * g.K;
+    }
+    __device__ __forceinline__ static int64_t source_rows(const Args &g, int, int64_t row0)
+    {
+        return g.n - row0;
+    }
+    __device__ __forceinline__ static void epilogue(const Args &g, v16i (&acc)[P][RB][CB],
+                                                    int64_t row0, int64_t col0, int wm, int wn,
+                                                    int lane)
+    {
+        const int64_t W = (g.N + 31) / 32;
+        unsigned long long cnt = 0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+            const int64_t cblk = col0 + (wn * CB + j) * 32;
+            const int64_t col = cblk + acc_col(lane);
+            const int64_t word = cblk / 32;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t row = row0 + wm * 32 + acc_row(r, lane);
+                const bool valid = row < g.n && col < g.N;
+                int v[P];
+#pragma unroll
+                for (int s = 0; s < P; ++s)
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(v[s]) : "a"(acc[s][0][j][r]));
+                int64_t sum = 0;
+#pragma unroll
+                for (int s = 0; s < M; ++s)
+                    sum += v[s];
+                const int64_t e = (int64_t)v[M] + (int64_t)v[M + 1] * 256;
+                const bool flag = valid && sum != e;
+                if (valid) {
+#pragma unroll
+                    for (int s = 0; s < M; ++s)
+                        g.d[((int64_t)s * g.n + row) * g.N + col] = v[s];
+                }
+                const uint64_t mask = __ballot(flag);
+                if (g.flags && word < W && row < g.n && (lane & 31) == 0)
+                    g.flags[row * W + word] = (uint32_t)(lane ? (mask >> 32) : mask);
+                cnt += (unsigned long long)__popcll(mask);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        if (g.n_bad && lane == 0 && cnt)
+            atomicAdd(g.n_bad, cnt);
+    }
+};
+
+// The checksum stream of the ABFT baseline as two balanced int8 digit
+// planes: r = sum_m c[m] = lo + 256 hi, 16 bytes per thread (count a
+// multiple of 16, every row 16-byte aligned).
+template <int M>
+__global__ __launch_bounds__(kThreads) void k_abft_checksum(const int8_t *__restrict__ c,
+                                                            int8_t *__restrict__ lo,
+                                                            int8_t *__restrict__ hi,
+                                                            int64_t count)
+{
+    const int64_t stride = (int64_t)gridDim.x * kThreads * 16;
+    for (int64_t i = ((int64_t)blockIdx.x * kThreads + threadIdx.x) * 16; i < count; i += stride) {
+        v4i x[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            x[m] = *(const v4i *)(c + (int64_t)m * count + i);
+        uint32_t l[4] = {0, 0, 0, 0}, h[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int sum = 0;
+#pragma unroll
+            for (int m = 0; m < M; ++m)
+                sum += (int)(int8_t)((uint32_t)x[m][e >> 2] >> (8 * (e & 3)));
+            const int d0 = (int)(int8_t)(sum & 0xFF);
+            const int d1 = (sum - d0) >> 8;
+            l[e >> 2] |= (uint32_t)(uint8_t)d0 << (8 * (e & 3));
+            h[e >> 2] |= (uint32_t)(uint8_t)d1 << (8 * (e & 3));
+        }
+        *(v4i *)(lo + i) = v4i{(int)l[0], (int)l[1], (int)l[2], (int)l[3]};
+        *(v4i *)(hi + i) = v4i{(int)h[0], (int)h[1], (int)h[2], (int)h[3]};
+    }
+}
 
 } // namespace
 } // namespace ne

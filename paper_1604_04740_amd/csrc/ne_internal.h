@@ -60,8 +60,10 @@ int launch_gemm_fused(const int8_t *c, const int8_t *Bt, void *dhat, int out64, 
 int launch_series_gemm(const int8_t *c, const int8_t *Bt, const int64_t *scale, const int64_t *add,
                        int64_t *rows, int64_t n, int64_t K, int64_t N, int M, int l, int r,
                        hipStream_t s);
+// ws: 2 n K bytes for the checksum digit planes (DMA pipeline), or NULL
+// (the checksum built in the prologue).
 int launch_gemm_abft(const int8_t *c, const int8_t *Bt, int32_t *d, uint32_t *flags,
-                     unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M,
+                     unsigned long long *n_bad, int64_t n, int64_t K, int64_t N, int M, void *ws,
                      hipStream_t s);
 
 // ---- circular convolution (ne_conv.hip) ----

@@ -287,16 +287,20 @@ def test_plain_gemm(ne, R, K, N):
     assert np.array_equal(_h(got).astype(np.int64), ref)
 
 
-@pytest.mark.parametrize("M,n,K,N", [(4, 64, 128, 128), (3, 33, 17, 45), (8, 40, 64, 100)])
+@pytest.mark.parametrize("M,n,K,N", [(4, 64, 128, 128), (3, 33, 17, 45), (8, 40, 64, 100),
+                                     (4, 70, 272, 300), (1, 5, 16, 7)])
 def test_abft_gemm(ne, orc, M, n, K, N):
     c, G = ne_synth.gemm_streams(1200 + M, M, n, K, N, -128, 128)
-    d, fl, nb = ne.ne_abft_gemm_i8(_t(c), _t(np.ascontiguousarray(G.T)))
     c64 = c.astype(np.int64)
     plain = np.stack([c64[m] @ G.astype(np.int64) for m in range(M)])
-    assert np.array_equal(_h(d).astype(np.int64), plain)
     e = orc.gemm(orc.abft_checksum(c64), G)
     flags_o, bad_o = orc.abft_check(plain, e)
-    assert bad_o == 0 and int(nb.item()) == 0 and not _bits(_h(fl), N).any()
+    assert bad_o == 0
+    # checksum planes + DMA pipeline (used when K % 16 == 0), and one launch
+    for ws in (True, None):
+        d, fl, nb = ne.ne_abft_gemm_i8(_t(c), _t(np.ascontiguousarray(G.T)), workspace=ws)
+        assert np.array_equal(_h(d).astype(np.int64), plain), ws
+        assert int(nb.item()) == 0 and not _bits(_h(fl), N).any(), ws
 
 
 # ---------------------------------------------- fault trials (small GEMM)
