@@ -147,10 +147,21 @@ def cpu_baseline_gemm(c, G, target_s: float):
     assert out["n_bad"] == 0
     Mc, _, Kc = c.shape
     ops = 2.0 * Mc * rows * Kc * G.shape[1]
-    return oracle_line(ops / dt / 1e12, "TOP/s",
+    # the same on one thread, on a sample sized for about 3 s
+    rows1 = max(1, min(rows, int(rows * 3.0 / max(dt, 1e-3) / max(threads(), 1))))
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.gemm_pipeline(c[:, :rows1, :], G)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads())
+    single = {"value": 2.0 * Mc * rows1 * Kc * G.shape[1] / dt1 / 1e12, "unit": "TOP/s",
+              "sample": f"first {rows1} rows; {dt1:.2f} s wall"}
+    return dict(oracle_line(ops / dt / 1e12, "TOP/s",
                        f"first {rows} rows of each of the {Mc} streams (all {G.shape[1]} columns, "
                        f"K={Kc}); entangle + int64 GEMM on entangled words + extract + check; "
-                       f"{dt:.2f} s wall"), out, rows
+                       f"{dt:.2f} s wall"), single_thread=single), out, rows
 
 
 def run_gemm(args, ne, ne_synth, np, torch, dev):

@@ -90,6 +90,12 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Number of OpenMP threads the oracle's loops use from now on."""
+    lib()
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 def _a64(x) -> np.ndarray:
     return np.ascontiguousarray(x, dtype=np.int64)
 
