@@ -506,11 +506,13 @@ typedef struct ne_batch ne_batch_t; /* opaque host-side plan */
 /*
  * Plan a batch: validates every problem, splits it into work items (GEMM
  * output tiles, 1024-position convolution blocks, permute/scale chunks: a
- * copy of the inputs into rows, then the gather), deals them to one list
- * per XCD (a GEMM's tiles in eight runs of neighbouring tiles, so that the
- * tiles sharing an L2 share operands; the other items in turn), orders each
- * list longest-first, and writes the problem table, the lists and room for
- * the row copies into the caller's device buffer table_dev (256-byte
+ * copy of the inputs into rows, then the gather), deals them to the XCDs (a
+ * GEMM's tiles in eight runs of neighbouring tiles, so that the tiles
+ * sharing an L2 share operands; the other items in turn), balances each
+ * XCD's items over its workgroups by a cost estimate (longest first, each
+ * to the least loaded workgroup), and writes the problem table, the
+ * per-workgroup lists and room for the row copies into the caller's device
+ * buffer table_dev (256-byte
  * aligned, table_bytes long; it must not be in use by a pending run).  With
  * table_dev == NULL only *table_needed is set.  tuning may be NULL
  * (defaults).  On success *plan is a small host object (the only thing the
@@ -524,8 +526,7 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
 /*
  * Run a planned batch: two persistent launches (one workgroup per compute
  * unit): GEMM tiles, convolution blocks and row copies, then the
- * permutation gathers.  The workgroups of an XCD take its list's items in
- * turn.  Plain kernels only, so the call can be captured into a HIP graph
+ * permutation gathers.  Each workgroup runs the list the plan gave it.  Plain kernels only, so the call can be captured into a HIP graph
  * and replayed.  Runs that share a table must not overlap (the row copies
  * live in the table).
  */

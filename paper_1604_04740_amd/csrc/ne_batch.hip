@@ -4,20 +4,20 @@
 // Host side (setup, not graph-capturable): ne_batch_plan turns a problem
 // list into work items -- one per GEMM output tile, one per 1024-position
 // convolution block, two per permute/scale chunk (copy of the inputs into
-// rows, then the gather) -- orders them longest-first by a cost estimate
-// (so the long items start early and the short ones fill the tail), and
-// writes the problem table, the item list and room for the row copies into
-// a caller-provided device buffer.  ne_batch_autotune times the candidate
+// rows, then the gather) -- deals them to the XCDs (a GEMM's tiles in eight
+// runs of neighbouring tiles, the other items in turn), balances each XCD's
+// items over its workgroups longest-first by a cost estimate (each item to
+// the least loaded workgroup), and writes the problem table, the per-
+// workgroup item lists and room for the row copies into a caller-provided
+// device buffer.  ne_batch_autotune times the candidate
 // tile choices of every (operation, M, size-class) bucket on the device and
 // returns the fastest per bucket.
 //
 // Device side: ne_batch_run launches the persistent kernel twice (grid =
 // one workgroup per CU): phase 0 runs every GEMM tile, convolution block and
-// row copy, phase 1 the permutation gathers that read those rows.  Items
-// are dealt to eight lists, one per XCD (a GEMM's tiles in eight runs of
-// neighbouring tiles, the other items in turn), each longest-first; the
-// workgroups of an XCD take its list's items in turn.  Every loop is
-// bounded by the item counts in the table, so the grid always drains.  Both
+// row copy, phase 1 the permutation gathers that read those rows.  Each
+// workgroup runs its own list.  Every loop is bounded by the list bounds in
+// the table, so the grid always drains.  Both
 // launches are plain kernels (no memset nodes), so ne_batch_run can be
 // captured in a HIP graph and replayed.
 #include <algorithm>
@@ -58,13 +58,13 @@ struct DevItem {
 };
 
 // Two phases, one launch each: the second (permutation gathers) reads the
-// row copies the first wrote.  Each phase keeps one item list per XCD:
-// list x of phase p is items[first[p][x] .. first[p][x] + count[p][x]).
+// row copies the first wrote.  Each phase keeps one item list per
+// workgroup: workgroup w of phase p runs items[wg[p][w] .. wg[p][w + 1]),
+// wg an int32 array [2][grid + 1] at wg_off.
 constexpr int kXcds = 8;
 struct DevHeader {
-    int32_t first[2][kXcds], count[2][kXcds];
-    int32_t n_problems, pad;
-    int64_t problems_off, items_off;
+    int32_t grid, n_problems;
+    int64_t problems_off, items_off, wg_off;
 };
 
 constexpr int64_t kHeaderBytes = 256;
@@ -222,20 +222,20 @@ static_assert(dma_lds_bytes<FusedV<8, 128>, kGemmBK, kGemmStages>() <= kBatchLds
 static_assert(cv_lds_bytes(kCvMaxSlots) <= kBatchLds, "LDS");
 static_assert(sizeof(DevHeader) <= kHeaderBytes, "header");
 
-// Workgroup w runs on XCD w mod 8 (workgroups are placed on the XCDs in
-// turn) and takes every (gridDim / 8)-th item of that XCD's list, starting
-// at w / 8: the tiles that share an XCD's L2 are neighbours in their
-// problem, and no item is fetched through a global counter.
+// Workgroup w (on XCD w mod 8: workgroups are placed on the XCDs in turn)
+// runs its own list, which the plan filled from that XCD's items: the tiles
+// that share an XCD's L2 are neighbours in their problem, and no item is
+// fetched through a global counter.
 __global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table, int phase)
 {
     __shared__ __attribute__((aligned(1024))) int8_t lds[kBatchLds];
     const auto *h = (const DevHeader *)table;
     const auto *problems = (const DevProblem *)(table + h->problems_off);
     const auto *items = (const DevItem *)(table + h->items_off);
-    const int x = blockIdx.x % kXcds, per = gridDim.x / kXcds;
-    const int first = uni(h->first[phase][x]), count = uni(h->count[phase][x]);
-    for (int i = blockIdx.x / kXcds; i < count; i += per) {
-        const DevItem im0 = items[first + i];
+    const auto *wg = (const int32_t *)(table + h->wg_off) + phase * (uni(h->grid) + 1);
+    const int lo = uni(wg[blockIdx.x]), hi = uni(wg[blockIdx.x + 1]);
+    for (int i = lo; i < hi; ++i) {
+        const DevItem im0 = items[i];
         const DevItem im = {uni(im0.problem), uni(im0.a), uni(im0.b), uni(im0.kind)};
         const DevProblem P = uniform(problems[im.problem]);
         if (P.op == NE_OP_GEMM)
@@ -319,26 +319,31 @@ int validate(const ne_problem_t &q, const ne_params_t &p)
     return NE_OK;
 }
 
-// Cost estimate (seconds on one CU) used only to order items longest-first.
+// Cost estimate (seconds on one CU, from the standalone kernels' measured
+// rates) used to balance the workgroups' lists.
 double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
 {
-    if (q.op == NE_OP_GEMM)
-        return 2.0 * 2.0 * q.M * 32.0 * bn * q.K / 8.0e12;
-    if (q.op == NE_OP_CONV)
-        return 3.0 * q.M * kCvBlock * q.N / 4.0e12; // matrix-core MACs + staging
+    if (q.op == NE_OP_GEMM) // matrix-core work at ~7.8 TOP/s per CU, plus the epilogue
+        return 2.0 * 2.0 * q.M * 32.0 * bn * q.K / 7.8e12 + 1.0e-6;
+    if (q.op == NE_OP_CONV) { // ~2.6 us per staged 256-tap step; M > 4 takes two passes
+        const double steps = (double)((q.N + kCvStep - 1) / kCvStep);
+        return (q.M > 4 ? 2.0 : 1.0) * (steps * 2.6e-6 + 4.0e-6);
+    }
     return (double)chunk * q.M * (1.0 + q.out_dtype) / 2.0e10;
 }
 
 struct Built {
     std::vector<DevProblem> probs;
-    std::vector<DevItem> items; // by phase, then by XCD
-    int first[2][kXcds] = {}, count[2][kXcds] = {};
+    std::vector<DevItem> items; // by phase, then by workgroup
+    std::vector<int32_t> wg;    // [2][grid + 1] list boundaries
+    int grid = 0;
     int n_phase[2] = {};
     std::vector<int64_t> rows_off; // per problem, offset of its row copy (or -1)
     int64_t rows_bytes = 0;
 };
 
-int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuning, Built &out)
+int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuning, int grid,
+          Built &out)
 {
     struct Tmp {
         DevItem it;
@@ -417,21 +422,35 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
             }
         }
     }
-    // every XCD list longest-first (stable: a problem's run keeps its order)
+    // Each XCD's items, longest first (stable: a problem's run keeps its
+    // order), go one by one to the least loaded of that XCD's workgroups
+    // (w = x, x + 8, ...); each workgroup runs its items longest first.
     auto by_xcd_cost = [](const Tmp &a, const Tmp &b) {
         return a.xcd != b.xcd ? a.xcd < b.xcd : a.cost > b.cost;
     };
+    const int per = grid / kXcds;
+    out.grid = grid;
     out.items.clear();
+    out.wg.assign(2 * (grid + 1), 0);
     for (int ph = 0; ph < 2; ++ph) {
         std::stable_sort(tmp[ph].begin(), tmp[ph].end(), by_xcd_cost);
         out.n_phase[ph] = (int)tmp[ph].size();
+        std::vector<std::vector<DevItem>> lists(grid);
+        size_t i = 0;
         for (int x = 0; x < kXcds; ++x) {
-            out.first[ph][x] = (int)out.items.size();
-            for (const Tmp &t : tmp[ph])
-                if (t.xcd == x)
-                    out.items.push_back(t.it);
-            out.count[ph][x] = (int)out.items.size() - out.first[ph][x];
+            std::vector<double> load(per, 0.0);
+            for (; i < tmp[ph].size() && tmp[ph][i].xcd == x; ++i) {
+                const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[k] += tmp[ph][i].cost;
+                lists[x + kXcds * k].push_back(tmp[ph][i].it);
+            }
         }
+        int32_t *wg = out.wg.data() + ph * (grid + 1);
+        for (int w = 0; w < grid; ++w) {
+            wg[w] = (int32_t)out.items.size();
+            out.items.insert(out.items.end(), lists[w].begin(), lists[w].end());
+        }
+        wg[grid] = (int32_t)out.items.size();
     }
     return NE_OK;
 }
@@ -440,7 +459,8 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
 int64_t table_head_bytes(const Built &b)
 {
     const int64_t h = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem) +
-                      (int64_t)b.items.size() * sizeof(DevItem);
+                      (int64_t)b.items.size() * sizeof(DevItem) +
+                      (int64_t)b.wg.size() * sizeof(int32_t);
     return (h + 255) / 256 * 256;
 }
 
@@ -454,14 +474,11 @@ int upload(Built &b, void *table_dev)
     const int64_t head = table_head_bytes(b);
     std::vector<uint8_t> host(head, 0);
     DevHeader h{};
-    for (int ph = 0; ph < 2; ++ph)
-        for (int x = 0; x < kXcds; ++x) {
-            h.first[ph][x] = b.first[ph][x];
-            h.count[ph][x] = b.count[ph][x];
-        }
+    h.grid = b.grid;
     h.n_problems = (int32_t)b.probs.size();
     h.problems_off = kHeaderBytes;
     h.items_off = kHeaderBytes + (int64_t)b.probs.size() * sizeof(DevProblem);
+    h.wg_off = h.items_off + (int64_t)b.items.size() * sizeof(DevItem);
     for (size_t i = 0; i < b.probs.size(); ++i)
         b.probs[i].rows = b.rows_off[i] < 0 ? nullptr
                                             : (uint64_t *)((uint8_t *)table_dev + head +
@@ -471,6 +488,7 @@ int upload(Built &b, void *table_dev)
         memcpy(host.data() + h.problems_off, b.probs.data(), b.probs.size() * sizeof(DevProblem));
     if (!b.items.empty())
         memcpy(host.data() + h.items_off, b.items.data(), b.items.size() * sizeof(DevItem));
+    memcpy(host.data() + h.wg_off, b.wg.data(), b.wg.size() * sizeof(int32_t));
     return hipMemcpy(table_dev, host.data(), host.size(), hipMemcpyHostToDevice) == hipSuccess
                ? NE_OK
                : NE_ELAUNCH;
@@ -510,7 +528,8 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
     if (count < 0 || (count > 0 && !problems) || !table_needed)
         return NE_EINVAL;
     Built b;
-    int rc = build(problems, count, tuning, b);
+    const int grid = std::max(kXcds, cu_count() / kXcds * kXcds);
+    int rc = build(problems, count, tuning, grid, b);
     if (rc)
         return rc;
     *table_needed = table_bytes(b);
@@ -528,7 +547,7 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
     bp->bytes = *table_needed;
     bp->n_items[0] = b.n_phase[0];
     bp->n_items[1] = b.n_phase[1];
-    bp->grid = std::max(kXcds, cu_count() / kXcds * kXcds);
+    bp->grid = grid;
     *plan = (ne_batch_t *)bp;
     return NE_OK;
 }
