@@ -438,17 +438,34 @@ def run_linconv(args, ne, ne_synth, np, torch, dev):
         out = torch.empty((M, no), dtype=torch.int32, device=dev)
         fl = torch.empty(((no + 31) // 32,), dtype=torch.int32, device=dev)
         nb = torch.zeros((1,), dtype=torch.int64, device=dev)
-        t = time_launches(lambda: ne.ne_linconv_fused(c_d, g_d, p, c_bits=15, out_dtype=torch.int32,
-                                                      out=out, flags=fl, n_bad=nb),
-                          args.steps, args.warmup, torch)
+        # both ways of staging the operands: from c directly, and from the
+        # digit planes of the pre-pass (workspace); the line takes the one
+        # the binding picks by default for this shape
+        ws = torch.empty((ne.ne_linconv_workspace(nx, L, M, 15, True) // 8 + 2,),
+                         dtype=torch.int64, device=dev)
+        run = lambda w: time_launches(
+            lambda: ne.ne_linconv_fused(c_d, g_d, p, c_bits=15, out_dtype=torch.int32, out=out,
+                                        flags=fl, n_bad=nb, workspace=w),
+            args.steps, args.warmup, torch)
+        t_planes = run(ws)
+        ref = out.clone()
+        t_direct = run(False)
+        assert torch.equal(ref, out), "the two staging paths differ"
+        del ref
+        planes = ne.linconv_planes_default(M, L)
+        t = t_planes if planes else t_direct
         assert int(nb.item()) == 0, "clean run flagged positions"
-        res = {"M": M, "taps": L, "ms": t, "useful_tops": 2.0 * M * nx * L / (t * 1e-3) / 1e12}
+        res = {"M": M, "taps": L, "ms": t, "useful_tops": 2.0 * M * nx * L / (t * 1e-3) / 1e12,
+               "staging": "planes" if planes else "direct", "planes_ms": t_planes,
+               "direct_ms": t_direct}
+        del ws
         if with_plain:
             # the same convolutions without entanglement: M plain streams on
             # the staged kernel (one product per stream instead of two)
             c64 = c_d.to(torch.int64)
             d = torch.empty((M, no), dtype=torch.int64, device=dev)
-            tp = time_launches(lambda: ne.ne_lsb_linconv(c64, 15, g_d, p, out=d), args.steps,
+            tp = time_launches(lambda: ne.ne_lsb_linconv(c64, 15, g_d, p, out=d,
+                                                         workspace=None), args.steps,
                                args.warmup, torch)
             assert torch.equal(d.to(torch.int32), out), "fused d_hat differs from the plain conv"
             res["plain_ms"] = tp
@@ -503,9 +520,14 @@ def run_linconv(args, ne, ne_synth, np, torch, dev):
                      "shared 4500-tap kernel U[-128,128) (int8); fused entangle + conv + "
                      "disentangle + check, int32 d_hat",
                      {"M": M, "samples": nx, "taps": L, "l": ne.ne_params_default(M).l,
-                      "k": ne.ne_params_default(M).k, "w": 64, "digits": digits})
+                      "k": ne.ne_params_default(M).k, "w": 64, "digits": digits,
+                      "staging": main["staging"]})
+    # achieved over the whole entry (with planes: the digit-plane pre-pass
+    # and the convolution kernel), so slightly below the kernel's own rate
     line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
                         "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None}
+    line["planes_ms"] = main["planes_ms"]
+    line["direct_ms"] = main["direct_ms"]
     line["cpu_baseline"] = cpu
     line["plain_ms"] = main["plain_ms"]
     line["overhead_vs_plain_pct"] = main["overhead_vs_plain_pct"]

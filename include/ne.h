@@ -166,10 +166,27 @@ int ne_lsb_circconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64
  *   eps       device, [M][N] int64; eps_bits as for ne_lsb_gemm.
  *   g         device, [L] int8.
  *   delta     device, [M][N + L - 1] int64; must not overlap eps or g.
+ *   workspace device scratch of ne_linconv_workspace(N, L, M, eps_bits, 0)
+ *             bytes (16-byte aligned, overlapping no other buffer), or
+ *             NULL.  With a workspace a pre-pass writes the int8 digits of
+ *             every stream, zero-padded, as byte planes, and the blocks
+ *             stage their operands from them with aligned 4-byte loads and
+ *             no bounds tests; with NULL the blocks form the digits from
+ *             eps themselves.  Results are identical.  Contents on entry do
+ *             not matter; a smaller workspace is NE_EINVAL.
  *   N >= 1, 1 <= L <= 131071, N + L - 1 <= 2^30 (else NE_EINVAL).
  */
 int ne_lsb_linconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t L,
-                   int64_t *delta, int64_t N, const ne_params_t *p, ne_stream_t stream);
+                   int64_t *delta, int64_t N, const ne_params_t *p, void *workspace,
+                   int64_t workspace_bytes, ne_stream_t stream);
+
+/*
+ * Workspace bytes of ne_lsb_linconv (fused = 0, bits = eps_bits) and
+ * ne_linconv_fused (fused = 1, bits = c_bits) for M streams of N samples
+ * and L taps: M * digits * planes of about N + 2 L + 4096 bytes each, plus
+ * L + 1024 bytes for the padded taps; 0 for invalid sizes.
+ */
+int64_t ne_linconv_workspace(int64_t N, int64_t L, int32_t M, int32_t bits, int32_t fused);
 
 /*
  * Workspace bytes that ne_lsb_circconv (fused = 0) or ne_circconv_fused
@@ -360,12 +377,15 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm,
  *   d_hat     device, [M][N + L - 1] of out_dtype (NE_I32 or NE_I64).
  *   flags     device, [ceil((N + L - 1) / 32)] uint32, or NULL; n_bad as
  *             usual.
+ *   workspace as for ne_lsb_linconv, ne_linconv_workspace(N, L, M, c_bits,
+ *             1) bytes, or NULL (the planes hold the digits of c).
  *   Sizes as for ne_lsb_linconv; NE_ERANGE unless L 2^(c_bits-1) 128 <= D.
  *   One workgroup per block of 1024 outputs; M <= 8.
  */
 int ne_linconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g, int64_t L,
                      void *d_hat, int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                     int64_t N, const ne_params_t *p, ne_stream_t stream);
+                     int64_t N, const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                     ne_stream_t stream);
 
 /*
  * Workspace bytes of ne_permute_scale_fused: N * ceil(M * c_dtype / 8) * 8;

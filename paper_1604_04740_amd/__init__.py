@@ -21,7 +21,7 @@ __all__ = [
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
     "ne_abft_workspace",
-    "ne_circconv_fused", "ne_circconv_workspace", "ne_permute_scale_fused", "ne_permute_workspace", "Inject", "Problem", "Batch", "ne_batch_plan",
+    "ne_circconv_fused", "ne_circconv_workspace", "ne_linconv_workspace", "linconv_planes_default", "ne_permute_scale_fused", "ne_permute_workspace", "Inject", "Problem", "Batch", "ne_batch_plan",
     "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
 
@@ -110,8 +110,10 @@ def lib():
             "ne_permute_scale_fused": ([_vp, _i32, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _i64, P,
                                         _vp, _i64, _vp], ctypes.c_int),
             "ne_permute_workspace": ([_i64, _i32, _i32], _i64),
-            "ne_lsb_linconv": ([_vp, _i32, _vp, _i64, _vp, _i64, P, _vp], ctypes.c_int),
-            "ne_linconv_fused": ([_vp, _i32, _i32, _vp, _i64, _vp, _i32, _vp, _vp, _i64, P, _vp],
+            "ne_lsb_linconv": ([_vp, _i32, _vp, _i64, _vp, _i64, P, _vp, _i64, _vp], ctypes.c_int),
+            "ne_linconv_workspace": ([_i64, _i64, _i32, _i32, _i32], _i64),
+            "ne_linconv_fused": ([_vp, _i32, _i32, _vp, _i64, _vp, _i32, _vp, _vp, _i64, P, _vp,
+                                  _i64, _vp],
                                  ctypes.c_int),
             "ne_series_range": ([P, _i64, _i32, ctypes.POINTER(_SeriesOp),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i64)], ctypes.c_int),
@@ -256,18 +258,52 @@ def ne_lsb_circconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params
     return out
 
 
+def ne_linconv_workspace(N: int, L: int, M: int, bits: int, fused: bool) -> int:
+    return int(lib().ne_linconv_workspace(N, L, M, bits, 1 if fused else 0))
+
+
+def linconv_planes_default(M: int, L: int) -> bool:
+    """Whether workspace=None stages a linear convolution from digit planes:
+    for kernels longer than four 256-tap steps (the blocks slide over the
+    taps) and six or more streams, where the per-step staging of the direct
+    path costs more than the pre-pass."""
+    return M >= 6 and L + 32 > 1024
+
+
+def _linconv_ws(workspace, N, L, M, bits, fused, device):
+    """workspace=True: allocate the digit planes the library asks for;
+    None: the same where linconv_planes_default says so; False: none."""
+    if workspace is None:
+        workspace = linconv_planes_default(M, L)
+    if workspace is True:
+        need = ne_linconv_workspace(N, L, M, bits, fused)
+        if need <= 0:
+            raise ValueError("invalid linear convolution sizes")
+        return torch.empty(((need + 15) // 16 * 2,), dtype=torch.int64, device=device)
+    if workspace is False:
+        return None
+    return workspace
+
+
+def _ws_args(ws):
+    return _opt(ws, "ws", None), ws.numel() * ws.element_size() if ws is not None else 0
+
+
 def ne_lsb_linconv(eps: torch.Tensor, eps_bits: int, g: torch.Tensor, p: Params,
-                   out: torch.Tensor | None = None) -> torch.Tensor:
-    """eps: [M, N] int64, g: [L] int8 -> delta [M, N + L - 1] int64 (linear convolution)."""
+                   out: torch.Tensor | None = None, workspace=None) -> torch.Tensor:
+    """eps: [M, N] int64, g: [L] int8 -> delta [M, N + L - 1] int64 (linear convolution).
+    workspace=True stages from digit planes written by a pre-pass (a tensor:
+    that buffer), False from eps directly, None as linconv_planes_default."""
     M, N = eps.shape
     (L,) = g.shape
     if M != p.M:
         raise ValueError("shape mismatch")
     if out is None:
         out = torch.empty((M, N + L - 1), dtype=torch.int64, device=eps.device)
+    ws = _linconv_ws(workspace, N, L, M, eps_bits, False, eps.device)
     _ok(lib().ne_lsb_linconv(_dev(eps, "eps", torch.int64), eps_bits, _dev(g, "g", torch.int8), L,
-                             _dev(out, "out", torch.int64), N, ctypes.byref(p), _stream()),
-        "ne_lsb_linconv")
+                             _dev(out, "out", torch.int64), N, ctypes.byref(p), *_ws_args(ws),
+                             _stream()), "ne_lsb_linconv")
     return out
 
 
@@ -462,9 +498,10 @@ def ne_circconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
 
 def ne_linconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
                      out_dtype=torch.int64, out: torch.Tensor | None = None,
-                     flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None):
+                     flags: bool | torch.Tensor = True, n_bad: torch.Tensor | None = None,
+                     workspace=None):
     """c: [M, N] int8/int32/int64, g: [L] int8 -> (d_hat [M, N + L - 1],
-    flags [ceil((N + L - 1) / 32)], n_bad)."""
+    flags [ceil((N + L - 1) / 32)], n_bad).  workspace as for ne_lsb_linconv."""
     M, N = c.shape
     (L,) = g.shape
     if M != p.M:
@@ -480,10 +517,11 @@ def ne_linconv_fused(c: torch.Tensor, g: torch.Tensor, p: Params, c_bits: int,
         flags = None
     if n_bad is None:
         n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    ws = _linconv_ws(workspace, N, L, M, c_bits, True, c.device)
     _ok(lib().ne_linconv_fused(_dev(c, "c"), _DT[c.dtype], c_bits, _dev(g, "g", torch.int8), L,
                                _dev(out, "out", out_dtype), _DT[out_dtype],
                                _opt(flags, "flags", torch.int32), _dev(n_bad, "n_bad", torch.int64),
-                               N, ctypes.byref(p), _stream()), "ne_linconv_fused")
+                               N, ctypes.byref(p), *_ws_args(ws), _stream()), "ne_linconv_fused")
     return out, flags, n_bad
 
 

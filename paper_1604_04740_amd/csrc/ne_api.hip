@@ -3,6 +3,9 @@
 // state; every launch goes to the caller's stream.
 #include <stdint.h>
 
+#include <initializer_list>
+#include <utility>
+
 #include "ne_arith.h"
 #include "ne_internal.h"
 
@@ -41,6 +44,23 @@ hipStream_t hs(ne_stream_t s) { return (hipStream_t)s; }
 bool linconv_sizes_ok(int64_t N, int64_t L)
 {
     return N >= 1 && L >= 1 && L <= kMaxK && N <= ((int64_t)1 << 30) - L + 1;
+}
+
+// A linear-convolution workspace: NULL, or at least need bytes, 16-byte
+// aligned and overlapping none of the buffers.
+int linconv_ws_ok(const void *ws, int64_t bytes, int64_t need,
+                  std::initializer_list<std::pair<const void *, int64_t>> bufs)
+{
+    if (!ws)
+        return NE_OK;
+    if (need <= 0 || bytes < need)
+        return NE_EINVAL;
+    for (const auto &b : bufs)
+        if (overlap(ws, need, b.first, b.second))
+            return NE_EALIAS;
+    if ((uintptr_t)ws % 16)
+        return NE_EALIGN;
+    return NE_OK;
 }
 
 } // namespace
@@ -454,8 +474,18 @@ int ne_permute_scale_fused(const void *c, int32_t c_dtype, const int32_t *perm, 
                                       hs(stream));
 }
 
+int64_t ne_linconv_workspace(int64_t N, int64_t L, int32_t M, int32_t bits, int32_t fused)
+{
+    if (!linconv_sizes_ok(N, L) || M < 3 || M > (fused ? kMaxStreamsFused : kMaxStreamsElementwise) ||
+        bits < 1 || bits > 64)
+        return 0;
+    return ne::linconv_workspace_bytes(N, L, M,
+                                       fused && bits <= 8 ? 1 : ne::digits_for_bits(bits));
+}
+
 int ne_lsb_linconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_t L,
-                   int64_t *delta, int64_t N, const ne_params_t *p, ne_stream_t stream)
+                   int64_t *delta, int64_t N, const ne_params_t *p, void *workspace,
+                   int64_t workspace_bytes, ne_stream_t stream)
 {
     int rc = check_params(p, kMaxStreamsElementwise);
     if (rc)
@@ -469,13 +499,18 @@ int ne_lsb_linconv(const int64_t *eps, int32_t eps_bits, const int8_t *g, int64_
         return NE_EALIAS;
     if ((uintptr_t)eps % 8 || (uintptr_t)delta % 8)
         return NE_EALIGN;
-    return launch_linconv_eps(eps, ne::digits_for_bits(eps_bits), g, L, delta, N, p->M,
+    rc = linconv_ws_ok(workspace, workspace_bytes, ne_linconv_workspace(N, L, p->M, eps_bits, 0),
+                       {{eps, ib}, {g, L}, {delta, ob}});
+    if (rc)
+        return rc;
+    return launch_linconv_eps(eps, ne::digits_for_bits(eps_bits), g, L, delta, N, p->M, workspace,
                               hs(stream));
 }
 
 int ne_linconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_t *g, int64_t L,
                      void *d_hat, int32_t out_dtype, uint32_t *flags, unsigned long long *n_bad,
-                     int64_t N, const ne_params_t *p, ne_stream_t stream)
+                     int64_t N, const ne_params_t *p, void *workspace, int64_t workspace_bytes,
+                     ne_stream_t stream)
 {
     int rc = check_params(p, kMaxStreamsFused);
     if (rc)
@@ -499,8 +534,13 @@ int ne_linconv_fused(const void *c, int32_t c_dtype, int32_t c_bits, const int8_
     if ((uintptr_t)c % c_dtype || (uintptr_t)d_hat % out_dtype || (uintptr_t)flags % 4 ||
         (uintptr_t)n_bad % 8)
         return NE_EALIGN;
+    rc = linconv_ws_ok(workspace, workspace_bytes, ne_linconv_workspace(N, L, p->M, c_bits, 1),
+                       {{c, N * p->M * c_dtype}, {g, L}, {d_hat, ob},
+                        {flags, ((No + 31) / 32) * 4}, {n_bad, 8}});
+    if (rc)
+        return rc;
     return launch_linconv_fused(c, c_dtype, c_bits, g, L, d_hat, out_dtype == NE_I64, flags, n_bad,
-                                N, p->M, p->l, p->r_check, hs(stream));
+                                N, p->M, p->l, p->r_check, workspace, hs(stream));
 }
 
 int ne_series_range(const ne_params_t *p, int64_t c_max, int32_t n_ops, const ne_series_op_t *ops,

@@ -132,8 +132,32 @@ int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *
 
 // ---------------------------------------------------- linear convolution
 
+// Workspace of the plane-staged linear form: the digit planes of M streams
+// and the padded copy of g.
+int64_t linconv_workspace_bytes(int64_t N, int64_t L, int M, int digits)
+{
+    return (int64_t)M * digits * cv_plane_bytes(N, L) + ((L + 2 * kCvGPad + 15) / 16) * 16;
+}
+
+namespace {
+// Planes and gpad in ws (linconv_workspace_bytes bytes): run the pre-pass
+// and point J at them.
+void linconv_planes(ConvJob &J, void *ws, hipStream_t s)
+{
+    J.P = cv_plane_bytes(J.N, J.L);
+    J.pad = cv_plane_pad(J.L);
+    int8_t *planes = (int8_t *)ws;
+    int8_t *gpad = planes + (int64_t)J.M * J.digits * J.P;
+    J.planes = planes;
+    J.gpad = gpad;
+    const int64_t dw = std::max(J.P, J.L + 2 * kCvGPad + 3) / 4;
+    k_cv_planes<<<dim3((unsigned)((dw + 255) / 256), (unsigned)(J.M + 1)), 256, 0, s>>>(J, planes,
+                                                                                         gpad);
+}
+} // namespace
+
 int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t L, int64_t *delta,
-                       int64_t N, int M, hipStream_t s)
+                       int64_t N, int M, void *ws, hipStream_t s)
 {
     ConvJob J{};
     J.x = eps;
@@ -148,6 +172,21 @@ int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t 
     J.M = M;
     const unsigned blocks = (unsigned)((J.Nout + kCvBlock - 1) / kCvBlock);
     const unsigned groups = (unsigned)((M + kCvMaxSlots - 1) / kCvMaxSlots);
+    if (M < 3 || M > kMaxStreamsElementwise)
+        return NE_EUNSUP;
+    if (ws) {
+        linconv_planes(J, ws, s);
+        switch (M) {
+        case 3: k_linconv_staged_pl<3><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+        case 4: k_linconv_staged_pl<4><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+        case 5: k_linconv_staged_pl<5><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+        case 6: k_linconv_staged_pl<6><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+        case 7: k_linconv_staged_pl<7><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
+        default:
+            k_linconv_staged_pl<kCvMaxSlots><<<dim3(blocks, groups), kCvThreads, 0, s>>>(J);
+        }
+        return launch_status();
+    }
     switch (M) {
     case 3: k_linconv_staged<3><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
     case 4: k_linconv_staged<4><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
@@ -155,8 +194,6 @@ int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t 
     case 6: k_linconv_staged<6><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
     case 7: k_linconv_staged<7><<<dim3(blocks, 1), kCvThreads, 0, s>>>(J); break;
     default:
-        if (M < 3 || M > kMaxStreamsElementwise)
-            return NE_EUNSUP;
         k_linconv_staged<kCvMaxSlots><<<dim3(blocks, groups), kCvThreads, 0, s>>>(J);
     }
     return launch_status();
@@ -164,7 +201,7 @@ int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t 
 
 int launch_linconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, int64_t L,
                          void *dhat, int out64, uint32_t *flags, unsigned long long *n_bad,
-                         int64_t N, int M, int l, int r, hipStream_t s)
+                         int64_t N, int M, int l, int r, void *ws, hipStream_t s)
 {
     ConvJob J{};
     J.x = c;
@@ -182,6 +219,20 @@ int launch_linconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g
     J.l = l;
     J.r = r;
     const unsigned blocks = (unsigned)((J.Nout + kCvBlock - 1) / kCvBlock);
+    if (M < 3 || M > 8)
+        return NE_EUNSUP;
+    if (ws) {
+        linconv_planes(J, ws, s);
+        switch (M) {
+        case 3: k_linconv_fused_pl<3><<<blocks, kCvThreads, 0, s>>>(J); break;
+        case 4: k_linconv_fused_pl<4><<<blocks, kCvThreads, 0, s>>>(J); break;
+        case 5: k_linconv_fused_pl<5><<<blocks, kCvThreads, 0, s>>>(J); break;
+        case 6: k_linconv_fused_pl<6><<<blocks, kCvThreads, 0, s>>>(J); break;
+        case 7: k_linconv_fused_pl<7><<<blocks, kCvThreads, 0, s>>>(J); break;
+        default: k_linconv_fused_pl<8><<<blocks, kCvThreads, 0, s>>>(J); break;
+        }
+        return launch_status();
+    }
     switch (M) {
     case 3: k_linconv_fused<3><<<blocks, kCvThreads, 0, s>>>(J); break;
     case 4: k_linconv_fused<4><<<blocks, kCvThreads, 0, s>>>(J); break;

@@ -67,6 +67,7 @@ constexpr int kCvGRing = 1024;    // bytes per g copy (>= 4 * 256)
 constexpr int kCvGStride = 1040;  // bytes between g copies (16 mod 256: bank spread)
 constexpr int kCvOneShot = 4;     // steps a workgroup stages at once
 constexpr int kCvMaxSlots = 8;
+constexpr int kCvGPad = 512;     // zero bytes around g in the plane-staged form (>= 290)
 
 // A rings allocated for G slots: at least eight, so that a one-shot
 // workgroup can hold every digit of up to eight (slot, digit) sources.
@@ -103,6 +104,11 @@ struct ConvJob {
     int64_t N;                  // samples per input stream
     int64_t L;                  // taps (circular: N)
     int64_t Nout;               // outputs per stream (circular: N; linear: N + L - 1)
+    // linear form with digit planes (k_cv_planes), or NULL:
+    const int8_t *planes;       // [M][digits][P]: digit d of sample j - pad at byte j
+    const int8_t *gpad;         // g with kCvGPad zero bytes on both sides
+    int64_t P;                  // bytes per plane (a multiple of 4)
+    int pad;                    // 3 mod 4
     int M, l, r;
     int s0;                     // staged: first stream of this workgroup
 };
@@ -232,6 +238,10 @@ struct CvG {
         if constexpr (LIN) {
             // B[i][p] = g[p + i - 32], zero outside the L taps
             const int L = (int)J.L, s = i0 + p - 32;
+            if (J.gpad && s >= -kCvGPad && s + 36 <= L + kCvGPad) {
+                gather_aligned(J.gpad + kCvGPad + s); // zero-padded copy of g
+                return;
+            }
             if (s >= 0 && s + 36 <= L) {
                 gather_aligned(J.g + s);
             } else {
@@ -299,6 +309,66 @@ struct CvG {
             t[k] = __builtin_amdgcn_alignbyte(w[k + 1], w[k], sh);
         *(cv4i *)dst = cv4i{(int)t[0], (int)t[1], (int)t[2], (int)t[3]};
         *(cv4i *)(dst + 16) = cv4i{(int)t[4], (int)t[5], (int)t[6], (int)t[7]};
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Linear form from digit planes.  A pre-pass (k_cv_planes) writes digit d
+// of every sample of stream m into plane (m, d) at byte j = index + pad,
+// zeros around the stream, and g with kCvGPad zero bytes on both sides.
+// Ring bytes v .. v + 3 (v a multiple of 4) hold samples t0 + 32 - v - k,
+// k = 0..3, which are the plane bytes o + 3 - k for o = t0 + 29 - v + pad,
+// a multiple of 4 since pad = 3 mod 4: one aligned dword, bytes reversed.
+// No bounds tests and no digit arithmetic remain in the staging.
+// ---------------------------------------------------------------------------
+
+__host__ __device__ constexpr int cv_plane_pad(int64_t L)
+{
+    return (int)(((L + 2048 + 3) / 4) * 4 + 3);
+}
+
+__host__ __device__ constexpr int64_t cv_plane_bytes(int64_t N, int64_t L)
+{
+    return ((N + 2 * (int64_t)cv_plane_pad(L) + 8 + 3) / 4) * 4;
+}
+
+// One thread's share of a round of A-ring dwords: NW plane dwords and the
+// ring byte offset each goes to (-1: none).
+template <int NW>
+struct CvP {
+    uint32_t w[NW];
+    int dst[NW];
+    // Dwords u0 + k * 256 + tid of the range: nrings rings of nd dwords from
+    // ring byte vb; ring rr is slot rr mod G of digit rr / G (alld) or of
+    // digit d.  Every lane loads (from the range's last dword past its end).
+    template <int G, bool FUSED>
+    __device__ __forceinline__ void load(const ConvJob &J, int t0i, int vb, int nd, int nrings,
+                                         bool alld, int d, int u0, int tid)
+    {
+        const int T = nrings * nd;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            const int u = u0 + k * kCvThreads + tid;
+            const int uc = u < T ? u : T - 1;
+            const int rr = uc / nd, q = uc - rr * nd;
+            const int s = rr % G, dig = alld ? rr / G : d;
+            const int v = vb + 4 * q;
+            int m;
+            if constexpr (FUSED)
+                m = (J.r + s) % J.M;
+            else
+                m = J.s0 + s < J.M ? J.s0 + s : 0; // slots past M: any valid plane
+            const int64_t o = (int64_t)(m * J.digits + dig) * J.P + (t0i + 29 - v + J.pad);
+            w[k] = *(const uint32_t *)(J.planes + o);
+            dst[k] = u < T ? (alld ? rr : s) * kCvRing + cv_ring_off(v) : -1;
+        }
+    }
+    __device__ __forceinline__ void store(int8_t *rings) const
+    {
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (dst[k] >= 0)
+                *(uint32_t *)(rings + dst[k]) = __builtin_amdgcn_perm(w[k], w[k], 0x00010203u);
     }
 };
 
@@ -473,6 +543,150 @@ __device__ __forceinline__ void conv_accumulate(const ConvJob &J, int64_t t0, in
     }
 }
 
+// conv_accumulate for the linear form from digit planes (J.planes): the
+// same tap loop, with each step's ring bytes staged as plane dwords and two
+// steps in flight (the registers of a step are a few dwords per thread).
+template <int G, bool FUSED, bool SPLIT = false>
+__device__ __forceinline__ void conv_accumulate_pl(const ConvJob &J, int64_t t0, int Ia, int Ib,
+                                                   int8_t *lds)
+{
+    static_assert(FUSED || !SPLIT, "split passes are for the fused form");
+    constexpr int CH = (FUSED && !SPLIT) ? 2 * G : G; // accumulator sets
+    constexpr int HALVES = SPLIT ? 2 : 1;
+    constexpr int NWS = (G * 64 + kCvThreads - 1) / kCvThreads; // ring dwords per thread and step
+    int8_t *rings = lds;
+    int8_t *gc = lds + cv_rings(G) * kCvRing;
+    auto *red = cv_red(lds, G);
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int t0i = (int)t0;
+    const int Np = ((int)J.L + 32 + 31) & ~31;
+    const int steps = (Ib - Ia) / kCvStep;
+    const int a = lane & 31, h = lane >> 5;
+
+    for (int i = tid; i < G * kCvBlock; i += kCvThreads)
+        red[i] = 0;
+
+    for (int pass = 0; pass < J.digits * HALVES; ++pass) {
+        const int d = pass / HALVES;
+        const bool prev = SPLIT && (pass & 1); // this pass: previous-stream products
+        cv16i acc[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+            for (int e = 0; e < 16; ++e)
+                acc[q][e] = 0;
+
+        // prologue: ring bytes [Ia - 992, Ia + span) and g taps
+        // [Ia, Ia + span) as in conv_accumulate
+        const bool oneshot = steps <= kCvOneShot;
+        const int span = oneshot ? steps * kCvStep : kCvStep;
+        const bool alld = oneshot && G * J.digits <= cv_rings(G);
+        const bool stage_a = !alld || pass == 0;
+        const bool stage_g = !oneshot || pass == 0;
+        const int dsel = alld ? d : 0; // ring group of this pass's digit
+        if (stage_a) {
+            const int nd = (992 + span) / 4, nr = alld ? G * J.digits : G;
+#pragma unroll 1
+            for (int u0 = 0; u0 < nr * nd; u0 += 4 * kCvThreads) {
+                CvP<4> b;
+                b.template load<G, FUSED>(J, t0i, Ia - 992, nd, nr, alld, d, u0, tid);
+                b.store(rings);
+            }
+        }
+        if (stage_g) {
+#pragma unroll 1
+            for (int j = 0; j < span / kCvStep; j += 2) {
+                CvG sg[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (j + u < span / kCvStep)
+                        sg[u].template load<true>(J, Ia + (j + u) * kCvStep, tid);
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    if (j + u < span / kCvStep)
+                        sg[u].store(gc);
+            }
+        }
+        // Two steps in flight: while step j is multiplied, step j + 2 is
+        // loaded and step j + 1 (loaded one step earlier) is stored; the loop
+        // is unrolled by two so that the register sets swap roles.
+        auto fetch = [&](CvP<NWS> &pp, CvG &gg, int jj) {
+            pp.template load<G, FUSED>(J, t0i, Ia + jj * kCvStep, kCvStep / 4, G, false, d, 0, tid);
+            gg.template load<true>(J, Ia + jj * kCvStep, tid);
+        };
+        CvP<NWS> pa, pb;
+        CvG ga, gb;
+        if (!oneshot && steps > 1)
+            fetch(pa, ga, 1);
+        __syncthreads();
+        auto step = [&](int j, CvP<NWS> &cur, CvG &gcur, CvP<NWS> &nxt, CvG &gnxt) {
+            const int I = Ia + j * kCvStep;
+            if (!oneshot && j + 2 < steps)
+                fetch(nxt, gnxt, j + 2);
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int i0 = I + 64 * wave + 32 * kk;
+                if (i0 < Np) {
+                    const cv4i B = *(const cv4i *)(gc + a * kCvGStride +
+                                                   ((i0 + 16 * h) & (kCvGRing - 1)));
+                    cv4i A[G];
+#pragma unroll
+                    for (int s = 0; s < G; ++s)
+                        A[s] = *(const cv4i *)(rings + (s + G * dsel) * kCvRing +
+                                               cv_ring_off(i0 + 16 * h - 32 * a));
+#pragma unroll
+                    for (int s = 0; s < G; ++s) {
+                        if constexpr (SPLIT) {
+                            acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                prev ? A[(s + G - 1) % G] : A[s], B, acc[s], 0, 0, 0);
+                        } else {
+                            acc[s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[s], B, acc[s], 0, 0,
+                                                                           0);
+                            if constexpr (FUSED)
+                                acc[G + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
+                                    A[(s + G - 1) % G], B, acc[G + s], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            if (!oneshot && j + 1 < steps) {
+                cur.store(rings);
+                gcur.store(gc);
+            }
+            if (!oneshot)
+                __syncthreads();
+        };
+        for (int j = 0; j < steps; j += 2) {
+            step(j, pa, ga, pb, gb);
+            if (j + 1 < steps)
+                step(j + 1, pb, gb, pa, ga);
+        }
+        if (oneshot)
+            __syncthreads(); // every wavefront's reads are done before the fold
+
+        // fold this digit's products into red (mod 2^64)
+#pragma unroll
+        for (int s = 0; s < G; ++s)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int row = 8 * (e >> 2) + 4 * h + (e & 3);
+                int lo, hi = 0;
+                asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(lo) : "a"(acc[s][e]));
+                if constexpr (FUSED && !SPLIT)
+                    asm volatile("v_accvgpr_read_b32 %0, %1" : "=v"(hi) : "a"(acc[G + s][e]));
+                uint64_t v = (uint64_t)(int64_t)lo;
+                if constexpr (FUSED && !SPLIT)
+                    v += (uint64_t)(int64_t)hi << J.l;
+                if constexpr (SPLIT)
+                    v = prev ? v << J.l : v;
+                atomicAdd(&red[s * kCvBlock + 32 * row + a], v << (8 * d));
+            }
+        __syncthreads();
+    }
+}
+
 // Finish one output position t of the fused form from the M delta words
 // of its slots: disentangle, check, store, and the wavefront's flag words
 // (the 64 lanes of a wavefront hold 64 consecutive positions starting at a
@@ -510,15 +724,20 @@ __device__ __forceinline__ void conv_finish(const ConvJob &J, const int (&stream
 
 // One whole block of 1024 outputs (all taps) in one workgroup.  FUSED:
 // G == M, disentangle and check; staged: write delta.
-template <int G, bool FUSED, bool SPLIT = false, bool LIN = false>
+// PL (linear form only): ring bytes from the digit planes of J.planes.
+template <int G, bool FUSED, bool SPLIT = false, bool LIN = false, bool PL = false>
 __device__ __forceinline__ void conv_block(const ConvJob &J, int64_t block, int8_t *lds)
 {
+    static_assert(LIN || !PL, "digit planes are for the linear form");
     int stream[G];
     cv_streams<G, FUSED>(J, stream);
     const int64_t t0 = block * kCvBlock;
     const int64_t span = LIN ? J.L + 32 : J.N;
     const int taps = (int)((span + kCvStep - 1) / kCvStep) * kCvStep;
-    conv_accumulate<G, FUSED, SPLIT, LIN>(J, t0, 0, taps, stream, lds);
+    if constexpr (PL)
+        conv_accumulate_pl<G, FUSED, SPLIT>(J, t0, 0, taps, lds);
+    else
+        conv_accumulate<G, FUSED, SPLIT, LIN>(J, t0, 0, taps, stream, lds);
     const auto *red = cv_red(lds, G);
     const int tid = threadIdx.x;
 #pragma unroll 1
@@ -571,6 +790,65 @@ __global__ __launch_bounds__(kCvThreads) void k_linconv_staged(ConvJob J)
     __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
     J.s0 = (int)blockIdx.y * G;
     conv_block<G, false, false, true>(J, blockIdx.x, lds);
+}
+
+template <int M>
+__global__ __launch_bounds__(kCvThreads) void k_linconv_fused_pl(const ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(M)];
+    conv_block<M, true, false, true, true>(J, blockIdx.x, lds);
+}
+
+template <int G>
+__global__ __launch_bounds__(kCvThreads) void k_linconv_staged_pl(ConvJob J)
+{
+    __shared__ __attribute__((aligned(16))) int8_t lds[cv_lds_bytes(G)];
+    J.s0 = (int)blockIdx.y * G;
+    conv_block<G, false, false, true, true>(J, blockIdx.x, lds);
+}
+
+// Pre-pass of the plane-staged linear form.  Row m < M of the grid writes
+// the digit planes of stream m (one dword of every plane per thread: plane
+// bytes 4q .. 4q + 3 hold digits of samples 4q - pad .. 4q - pad + 3, zero
+// outside the stream); row M writes g with kCvGPad zero bytes on both sides.
+__global__ __launch_bounds__(256) void k_cv_planes(const ConvJob J, int8_t *planes, int8_t *gpad)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int m = blockIdx.y;
+    if (m == J.M) {
+        const int64_t gbytes = J.L + 2 * kCvGPad;
+        if (4 * q >= gbytes)
+            return;
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t i = 4 * q + b - kCvGPad;
+            if (i >= 0 && i < J.L)
+                w |= (uint32_t)(uint8_t)J.g[i] << (8 * b);
+        }
+        *(uint32_t *)(gpad + 4 * q) = w;
+        return;
+    }
+    if (4 * q >= J.P)
+        return;
+    int64_t v[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int64_t i = 4 * q + b - J.pad;
+        const bool in = i >= 0 && i < J.N;
+        const int64_t ic = (int64_t)m * J.N + (in ? i : 0);
+        const int64_t x = J.x_dtype == NE_I64   ? ((const int64_t *)J.x)[ic]
+                          : J.x_dtype == NE_I32 ? ((const int32_t *)J.x)[ic]
+                                                : ((const int8_t *)J.x)[ic];
+        v[b] = in ? x : 0;
+    }
+    for (int d = 0; d < J.digits; ++d) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            w |= (uint32_t)(uint8_t)digit(v[b]) << (8 * b);
+        *(uint32_t *)(planes + ((int64_t)m * J.digits + d) * J.P + 4 * q) = w;
+    }
 }
 
 // Split taps: workgroup (block, z, group) accumulates taps [z KC, (z+1) KC)

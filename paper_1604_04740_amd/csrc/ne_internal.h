@@ -80,11 +80,13 @@ int launch_circconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *
                           int out64, uint32_t *flags, unsigned long long *n_bad, int64_t N, int M,
                           int l, int r, void *ws, hipStream_t s);
 // Linear convolution of N samples with L taps (N + L - 1 outputs per stream).
+// ws: linconv_workspace_bytes(N, L, M, digits) bytes (plane-staged) or NULL
+int64_t linconv_workspace_bytes(int64_t N, int64_t L, int M, int digits);
 int launch_linconv_eps(const int64_t *eps, int digits, const int8_t *g, int64_t L, int64_t *delta,
-                       int64_t N, int M, hipStream_t s);
+                       int64_t N, int M, void *ws, hipStream_t s);
 int launch_linconv_fused(const void *c, int c_dtype, int c_bits, const int8_t *g, int64_t L,
                          void *dhat, int out64, uint32_t *flags, unsigned long long *n_bad,
-                         int64_t N, int M, int l, int r, hipStream_t s);
+                         int64_t N, int M, int l, int r, void *ws, hipStream_t s);
 
 // Grid size for grid-stride element-wise kernels.
 inline unsigned grid_for(int64_t work, int threads)

@@ -217,8 +217,10 @@ def test_linconv_argument_errors(ne):
     p = ne.ne_params_default(4)
     fake = ctypes.c_void_p(1 << 20)
     fused = lambda N, L, bits: L_.ne_linconv_fused(fake, ne.NE_I32, bits, fake, L, fake,
-                                                   ne.NE_I64, None, None, N, ctypes.byref(p), None)
-    staged = lambda N, L: L_.ne_lsb_linconv(fake, 40, fake, L, fake, N, ctypes.byref(p), None)
+                                                   ne.NE_I64, None, None, N, ctypes.byref(p), None,
+                                                   0, None)
+    staged = lambda N, L: L_.ne_lsb_linconv(fake, 40, fake, L, fake, N, ctypes.byref(p), None, 0,
+                                            None)
     for N, L in [(0, 5), (5, 0), (-1, 5), (10, 131072), ((1 << 30) - 100, 200)]:
         assert fused(N, L, 15) == ne.NE_EINVAL, (N, L)
         assert staged(N, L) == ne.NE_EINVAL, (N, L)
@@ -226,3 +228,34 @@ def test_linconv_argument_errors(ne):
     assert fused(1000, 4500, 30) == ne.NE_ERANGE       # 4500 * 2^29 * 128 > D at M = 4
     assert fused(1000, 100, 15) == ne.NE_EALIAS        # everything at one address
     assert staged(1000, 100) == ne.NE_EALIAS
+
+
+def test_linconv_workspace(ne):
+    """Workspace size of the plane-staged linear convolution, and its
+    argument errors (all raised before any launch)."""
+    L_ = ne.lib()
+    pad = lambda L: (L + 2048 + 3) // 4 * 4 + 3
+    plane = lambda N, L: (N + 2 * pad(L) + 8 + 3) // 4 * 4
+    taps = lambda L: (L + 1024 + 15) // 16 * 16
+    # fused, c_bits 15: two digits; staged, eps_bits 40: six digits
+    assert L_.ne_linconv_workspace(1000, 100, 4, 15, 1) == 4 * 2 * plane(1000, 100) + taps(100)
+    assert L_.ne_linconv_workspace(1000, 100, 4, 8, 1) == 4 * 1 * plane(1000, 100) + taps(100)
+    assert L_.ne_linconv_workspace(1000, 100, 4, 8, 0) == 4 * 2 * plane(1000, 100) + taps(100)
+    assert L_.ne_linconv_workspace(10**6, 4500, 16, 40, 0) == 16 * 6 * plane(10**6, 4500) + taps(4500)
+    for args in [(0, 5, 4, 15, 1), (5, 0, 4, 15, 1), (10, 5, 2, 15, 1), (10, 5, 9, 15, 1),
+                 (10, 5, 4, 0, 0), (10, 5, 4, 65, 0), (10, 131072, 4, 15, 1)]:
+        assert L_.ne_linconv_workspace(*args) == 0, args
+    p = ne.ne_params_default(4)
+    c, g, d = (ctypes.c_void_p(a << 20) for a in (1, 2, 3))
+    need = L_.ne_linconv_workspace(1000, 100, 4, 15, 1)
+    fused = lambda ws, nb: L_.ne_linconv_fused(c, ne.NE_I32, 15, g, 100, d, ne.NE_I64, None, None,
+                                               1000, ctypes.byref(p), ctypes.c_void_p(ws), nb, None)
+    assert fused(64 << 20, need - 1) == ne.NE_EINVAL          # too small
+    assert fused(3 << 20, need) == ne.NE_EALIAS               # on top of d_hat
+    assert fused((64 << 20) + 8, need) == ne.NE_EALIGN        # not 16-byte aligned
+    needs = L_.ne_linconv_workspace(1000, 100, 4, 40, 0)
+    staged = lambda ws, nb: L_.ne_lsb_linconv(c, 40, g, 100, d, 1000, ctypes.byref(p),
+                                              ctypes.c_void_p(ws), nb, None)
+    assert staged(64 << 20, needs - 1) == ne.NE_EINVAL
+    assert staged(1 << 20, needs) == ne.NE_EALIAS             # on top of eps
+    assert staged((64 << 20) + 4, needs) == ne.NE_EALIGN
