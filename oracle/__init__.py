@@ -17,6 +17,9 @@ Parity status of each function (what pins it is listed in tests/):
                                 of the pinned circular convolution)
   extract, check, extract3      pinned (exhaustive tiny w, closed forms)
   abft_checksum, abft_check     pinned (sum identities, recovery)
+  abft_rc                       pinned (Python-int brute force; every 1-3
+                                wrong positions flagged, a +-e rectangle of
+                                four not; a single one at its row x column)
   series_bound, series_pipeline pinned (plain series in Python integers,
                                 homomorphism after every step, extremal
                                 inputs at the bound, tiny-w range edge)
@@ -258,6 +261,33 @@ def abft_recover(d, e, lost: int, w: int = 64) -> np.ndarray:
     M = d.shape[0]
     lib().ne_oracle_abft_check(_p(d), _p(e), None, M, d.size // M, w, lost)
     return d
+
+
+def abft_rc(c, G, d=None):
+    """Row/column checksum ABFT (Huang and Abraham), the "RC-check" baseline
+    of the GEMM comparison in section V, over M subblock products
+    d[m] = c[m] G (c [M][n][K], G [K][N]; d computed here when None).
+    The input checksums e^T c[m] and G e give the row sums c[m] (G e) and
+    the column sums (e^T c[m]) G that d[m] must have; a row or column whose
+    sum differs is flagged.  Returns d, row_bad [M][n], col_bad [M][N] and
+    n_bad (flagged rows plus columns).  Sums are 64-bit exact for the sizes
+    used here."""
+    c = _a64(c)
+    G = _a64(G)
+    M = c.shape[0]
+    if d is None:
+        d = np.stack([gemm(c[m], G) for m in range(M)])
+    d = _a64(d)
+    ge = G.sum(axis=1)                       # G e
+    row_bad = np.zeros(d.shape[:2], dtype=bool)
+    col_bad = np.zeros((M, d.shape[2]), dtype=bool)
+    for m in range(M):
+        row_ref = gemm(c[m], ge[:, None])[:, 0]
+        col_ref = gemm(c[m].sum(axis=0)[None, :], G)[0]
+        row_bad[m] = d[m].sum(axis=1) != row_ref
+        col_bad[m] = d[m].sum(axis=0) != col_ref
+    return {"d": d, "row_bad": row_bad, "col_bad": col_bad,
+            "n_bad": int(row_bad.sum() + col_bad.sum())}
 
 
 def opcount(which: str, M: float, N: float) -> float:

@@ -574,3 +574,75 @@ def test_linconv_pipeline(orc, M):
     delta[M - 1, 40] ^= 1 << 33
     _, flags, bad = orc.extract_check(delta, 64, l, 0)
     assert bad == 1 and flags[40] and flags.sum() == 1
+
+
+# ---------------------------------------------------------------------------
+# Row/column checksum ABFT (section V, the RC-check baseline)
+
+def test_abft_rc_brute_force(orc):
+    """d and both checksum comparisons against Python-integer loops over the
+    definitions (product, row sums, column sums) on a tiny ragged case."""
+    M, n, K, N = 2, 3, 5, 4
+    c = ne_synth.uniform_int(4100, 1, (M, n, K), -128, 128)
+    G = ne_synth.uniform_int(4100, 2, (K, N), -128, 128)
+    d = [[[sum(int(c[m, i, k]) * int(G[k, p]) for k in range(K)) for p in range(N)]
+          for i in range(n)] for m in range(M)]
+    got = orc.abft_rc(c, G)
+    assert got["d"].tolist() == d
+    assert got["n_bad"] == 0 and not got["row_bad"].any() and not got["col_bad"].any()
+    bad = [row[:] for row in d[1]]
+    bad[2][1] += 7
+    dd = np.array([d[0], bad])
+    got = orc.abft_rc(c, G, dd)
+    for i in range(n):
+        want = sum(bad[i]) != sum(int(c[1, i, k]) * sum(int(G[k, p]) for p in range(N))
+                                  for k in range(K))
+        assert got["row_bad"][1, i] == want
+    for p in range(N):
+        want = sum(bad[i][p] for i in range(n)) != sum(
+            sum(int(c[1, i, k]) for i in range(n)) * int(G[k, p]) for k in range(K))
+        assert got["col_bad"][1, p] == want
+    assert got["row_bad"][1].tolist() == [False, False, True]
+    assert got["col_bad"][1].tolist() == [False, True, False, False]
+    assert not got["row_bad"][0].any() and not got["col_bad"][0].any() and got["n_bad"] == 2
+
+
+def test_abft_rc_detects_up_to_three(orc):
+    """Every set of one to three wrong positions of a subblock is flagged
+    (the guarantee the paper quotes for the RC-check), and a single wrong
+    position is located at exactly its row and column."""
+    M, n, K, N = 3, 9, 12, 7
+    c = ne_synth.uniform_int(4200, 1, (M, n, K), -128, 128)
+    G = ne_synth.uniform_int(4200, 2, (K, N), -128, 128)
+    d = orc.abft_rc(c, G)["d"]
+    rng = np.random.default_rng(42)
+    for trial in range(300):
+        m = int(rng.integers(M))
+        cnt = 1 + trial % 3
+        pos = rng.choice(n * N, size=cnt, replace=False)
+        dd = d.copy()
+        for q in pos:
+            e = int(rng.integers(1, 1 << 20)) * (1 if rng.integers(2) else -1)
+            dd[m, q // N, q % N] += e
+        got = orc.abft_rc(c, G, dd)
+        assert got["n_bad"] > 0, (trial, pos)
+        others = [x for x in range(M) if x != m]
+        assert not got["row_bad"][others].any() and not got["col_bad"][others].any()
+        if cnt == 1:
+            i, p = divmod(int(pos[0]), N)
+            assert np.nonzero(got["row_bad"][m])[0].tolist() == [i]
+            assert np.nonzero(got["col_bad"][m])[0].tolist() == [p]
+
+
+def test_abft_rc_rectangle_undetected(orc):
+    """Four errors +e, -e, -e, +e at the corners of a rectangle cancel in
+    both sums: the RC-check's known blind spot (so four is not guaranteed)."""
+    M, n, K, N = 1, 6, 8, 5
+    c = ne_synth.uniform_int(4300, 1, (M, n, K), -128, 128)
+    G = ne_synth.uniform_int(4300, 2, (K, N), -128, 128)
+    d = orc.abft_rc(c, G)["d"]
+    d[0, 1, 0] += 5
+    d[0, 1, 3] -= 5
+    d[0, 4, 0] -= 5
+    d[0, 4, 3] += 5
+    assert orc.abft_rc(c, G, d)["n_bad"] == 0
