@@ -535,6 +535,116 @@ def run_linconv(args, ne, ne_synth, np, torch, dev):
     return line
 
 
+def run_rc(args, ne, ne_synth, np, torch, dev):
+    """The paper's GEMM comparison shape (section V): M = 4 subblock products
+    of 2000 x K by K x 1200, K = 200 .. 2000.  The line is the fused
+    entangled GEMM at K = 2000, beside the plain GEMM, the checksum-stream
+    ABFT and the row/column checksum ABFT (RC-check) of the same products;
+    the other K are extra fields."""
+    import oracle
+
+    seed = ne_synth.BASE_SEED + 8
+    Mr, nr, Nr = 4, 2000, 1200
+    p = ne.ne_params_default(Mr)
+
+    def measure(Kr):
+        c = ne_synth.uniform_int(seed, 1, (Mr, nr, Kr), -128, 128).astype(np.int8)
+        G = ne_synth.uniform_int(seed, 2, (Kr, Nr), -128, 128).astype(np.int8)
+        c_d = torch.from_numpy(c).to(dev)
+        gt_d = torch.from_numpy(np.ascontiguousarray(G.T)).to(dev)
+        out = torch.empty((Mr, nr, Nr), dtype=torch.int32, device=dev)
+        fl = torch.empty((nr, (Nr + 31) // 32), dtype=torch.int32, device=dev)
+        nb = torch.zeros((1,), dtype=torch.int64, device=dev)
+        t_ne = time_launches(lambda: ne.ne_gemm_fused(c_d, gt_d, p, out=out, flags=fl, n_bad=nb),
+                             args.steps, args.warmup, torch)
+        assert int(nb.item()) == 0, "clean run flagged positions"
+        C = torch.empty((Mr * nr, Nr), dtype=torch.int32, device=dev)
+        A = c_d.reshape(Mr * nr, Kr)
+        t_plain = time_launches(lambda: ne.ne_plain_gemm_i8(A, gt_d, out=C), args.steps,
+                                args.warmup, torch)
+        assert torch.equal(C.reshape(Mr, nr, Nr), out), "fused d_hat differs from the plain GEMM"
+        d_ab = torch.empty_like(out)
+        ws_ab = torch.empty((ne.ne_abft_workspace(nr, Kr) // 8 + 2,), dtype=torch.int64,
+                            device=dev)
+        t_abft = time_launches(lambda: ne.ne_abft_gemm_i8(c_d, gt_d, out=d_ab, flags=fl, n_bad=nb,
+                                                          workspace=ws_ab),
+                               args.steps, args.warmup, torch)
+        assert int(nb.item()) == 0 and torch.equal(d_ab, out), "checksum-stream ABFT"
+        d_rc = torch.empty_like(out)
+        rf = torch.empty((Mr, (nr + 31) // 32), dtype=torch.int32, device=dev)
+        cf = torch.empty((Mr, (Nr + 31) // 32), dtype=torch.int32, device=dev)
+        ws_rc = torch.empty((ne.ne_abft_rc_workspace(Mr, Kr, Nr) // 8 + 2,), dtype=torch.int64,
+                            device=dev)
+        t_rc = time_launches(lambda: ne.ne_abft_rc_gemm_i8(c_d, gt_d, d_rc, rf, cf, nb, ws_rc),
+                             args.steps, args.warmup, torch)
+        assert int(nb.item()) == 0 and torch.equal(d_rc, out), "RC-check ABFT"
+        useful = 2.0 * Mr * nr * Kr * Nr
+        res = {"K": Kr, "ne_ms": t_ne, "plain_ms": t_plain, "abft_ms": t_abft, "rc_ms": t_rc,
+               "ne_useful_tops": useful / (t_ne * 1e-3) / 1e12,
+               "overhead_ne_vs_plain_pct": 100.0 * (t_ne / t_plain - 1.0),
+               "overhead_abft_vs_plain_pct": 100.0 * (t_abft / t_plain - 1.0),
+               "overhead_rc_vs_plain_pct": 100.0 * (t_rc / t_plain - 1.0)}
+        return res, c, G, c_d, gt_d, d_rc, rf, cf, ws_rc
+
+    corners = []
+    for Kr in (200, 1000):
+        log(f"subblock GEMMs, K = {Kr}")
+        corners.append(measure(Kr)[0])
+    log("subblock GEMMs, K = 2000")
+    main, c, G, c_d, gt_d, d_rc, rf, cf, ws_rc = measure(2000)
+    Kr = 2000
+    # RC-check detection: one flipped bit per trial in a random position
+    log("RC-check detection of single wrong positions")
+    rng = np.random.default_rng(8)
+    trials, located = 64, 0
+    nb = torch.zeros((1,), dtype=torch.int64, device=dev)
+    for _ in range(trials):
+        m, i, q = int(rng.integers(Mr)), int(rng.integers(nr)), int(rng.integers(Nr))
+        keep = d_rc[m, i, q].clone()
+        d_rc[m, i, q] ^= 1 << int(rng.integers(31))
+        nb.zero_()
+        ne.ne_abft_rc_check_i8(c_d, gt_d, d_rc, rf, cf, nb, ws_rc)
+        rows = np.nonzero(((rf[m].cpu().numpy().astype(np.int64) & 0xFFFFFFFF)[:, None]
+                           >> np.arange(32)).reshape(-1) & 1)[0]
+        cols = np.nonzero(((cf[m].cpu().numpy().astype(np.int64) & 0xFFFFFFFF)[:, None]
+                           >> np.arange(32)).reshape(-1) & 1)[0]
+        located += int(int(nb.item()) == 2 and rows.tolist() == [i] and cols.tolist() == [q])
+        d_rc[m, i, q] = keep
+    t = main["ne_ms"]
+    issued = 2.0 * 2 * Mr * nr * Kr * Nr
+    achieved = issued / (t * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle baseline (RC-check ABFT)")
+        S = 16
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.abft_rc(c[:, :S], G)
+            dt = time.perf_counter() - t0
+            if dt >= args.cpu_seconds or S >= nr:
+                break
+            S = min(nr, max(S * 2, int(S * args.cpu_seconds / max(dt, 1e-3) * 1.1)))
+        assert ref["n_bad"] == 0
+        cpu = oracle_line(2.0 * Mr * S * Kr * Nr / dt / 1e12, "TOP/s",
+                          f"the first {S} rows of each of the {Mr} subblocks, K = {Kr}, all "
+                          f"{Nr} columns (int64 product + row/column checksum check); "
+                          f"{dt:.2f} s wall")
+    line = base_line(main["ne_useful_tops"], "TOP/s", args.steps, args.warmup, t, "i8",
+                     "subblock GEMMs of the paper's comparison: M=4 products of 2000x2000 by "
+                     "2000x1200, int8 U[-128,128); fused entangle + GEMM + disentangle + check, "
+                     "against plain, checksum-stream ABFT and row/column checksum ABFT",
+                     {"M": Mr, "n": nr, "K": Kr, "N": Nr, "l": p.l, "k": p.k, "w": 64})
+    line["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_TOPS,
+                        "unit": "TOP/s", "frac": achieved / PEAK_INT8_TOPS, "traffic": None}
+    line["cpu_baseline"] = cpu
+    for key in ("plain_ms", "abft_ms", "rc_ms", "overhead_ne_vs_plain_pct",
+                "overhead_abft_vs_plain_pct", "overhead_rc_vs_plain_pct"):
+        line[key] = main[key]
+    line["rc_detection"] = {"injected": trials, "located": located, "rate": located / trials}
+    line["corners"] = corners
+    return line
+
+
 def run_elementwise(args, ne, ne_synth, np, torch, dev):
     """The staged element-wise path (entangle, permute/scale/add on entangled
     words, disentangle + check) over M = 4 streams of 2^24 int32 samples, at
@@ -786,7 +896,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series", "linconv", "elementwise"], default="gemm")
+    ap.add_argument("--workload", choices=["gemm", "conv", "batch", "stress", "series", "linconv", "elementwise", "rc"], default="gemm")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--traffic-probe", action="store_true")
@@ -807,7 +917,8 @@ def main():
         traffic_probe(ne, ne_synth, np, torch, dev)
         return
     fn = {"gemm": run_gemm, "conv": run_conv, "batch": run_batch, "stress": run_stress,
-          "series": run_series, "linconv": run_linconv, "elementwise": run_elementwise}
+          "series": run_series, "linconv": run_linconv, "elementwise": run_elementwise,
+          "rc": run_rc}
     line = fn[args.workload](args, ne, ne_synth, np, torch, dev)
     print(json.dumps(line), flush=True)
 

@@ -315,6 +315,48 @@ int ne_abft_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *fla
 int64_t ne_abft_workspace(int64_t n, int64_t K);
 
 /*
+ * Baseline: row/column checksum ABFT (Huang and Abraham; the "RC-check" of
+ * the GEMM comparison in section V) for M independent subblock products
+ * d[m] = c[m] G.  The checksums of the inputs, e^T c[m] and G e (e all
+ * ones), give every row sum and column sum the product must have:
+ *     sum_p d[m][i][p] = c[m][i] . (G e),   sum_i d[m][i][p] = (e^T c[m]) . G[:, p]
+ * A row or column whose sum differs (exact 64-bit integers) is flagged; a
+ * wrong position is at the crossing of a flagged row and a flagged column,
+ * and up to three wrong positions per subblock are always detected.  The
+ * product itself is the plain int8 GEMM (ne_plain_gemm_i8); the checks are
+ * separate passes over c, G and d.
+ *   c          device [M][n][K] int8;  Gt device [N][K] int8 (G transposed).
+ *   d          device [M][n][N] int32 (written).
+ *   row_flags  device [M][ceil(n/32)] uint32, bit i % 32 of word
+ *              [m][i / 32] set for a flagged row, or NULL.
+ *   col_flags  device [M][ceil(N/32)] uint32, likewise for columns, or NULL.
+ *   n_bad      device counter, incremented by the number of flagged rows
+ *              and columns, or NULL.
+ *   workspace  device, ne_abft_rc_workspace(M, K, N) bytes, 16-byte aligned
+ *              (required; contents on entry do not matter).
+ *   1 <= M <= 4096, 1 <= n, N <= 2^20, 1 <= K <= 131071, else NE_EINVAL.
+ *   Written buffers must not overlap any other argument (NE_EALIAS).
+ */
+int ne_abft_rc_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *row_flags,
+                       uint32_t *col_flags, unsigned long long *n_bad, int32_t M, int64_t n,
+                       int64_t K, int64_t N, void *workspace, int64_t workspace_bytes,
+                       ne_stream_t stream);
+
+/*
+ * The check of ne_abft_rc_gemm_i8 alone, on a given product d (read
+ * only): for callers that compute the product themselves, and for fault
+ * injection into d.  Arguments as above.
+ */
+int ne_abft_rc_check_i8(const int8_t *c, const int8_t *Gt, const int32_t *d, uint32_t *row_flags,
+                        uint32_t *col_flags, unsigned long long *n_bad, int32_t M, int64_t n,
+                        int64_t K, int64_t N, void *workspace, int64_t workspace_bytes,
+                        ne_stream_t stream);
+
+/* Workspace bytes of the row/column checksum ABFT: 4 (M + 1) K rounded up
+ * to 16, plus 8 M N; 0 for invalid sizes. */
+int64_t ne_abft_rc_workspace(int32_t M, int64_t K, int64_t N);
+
+/*
  * Fused circular convolution, one launch: the star operator of section II on
  * the entangled words, then disentangle and check (section III-C).  delta
  * never reaches memory.  Each block of 1024 outputs is a Toeplitz x Hankel

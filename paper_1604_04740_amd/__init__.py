@@ -20,7 +20,7 @@ __all__ = [
     "NEError", "Params", "lib", "ne_version", "ne_strerror", "ne_params_default", "ne_range_bound",
     "ne_entangle", "ne_lsb_gemm", "ne_lsb_circconv", "ne_lsb_permute_scale",
     "ne_disentangle_check", "ne_recover", "ne_gemm_fused", "ne_plain_gemm_i8", "ne_abft_gemm_i8",
-    "ne_abft_workspace",
+    "ne_abft_workspace", "ne_abft_rc_gemm_i8", "ne_abft_rc_check_i8", "ne_abft_rc_workspace",
     "ne_circconv_fused", "ne_circconv_workspace", "ne_linconv_workspace", "linconv_planes_default", "ne_permute_scale_fused", "ne_permute_workspace", "Inject", "Problem", "Batch", "ne_batch_plan",
     "ne_batch_run", "ne_batch_autotune", "NE_OP_GEMM", "NE_OP_CONV", "NE_OP_PERM",
 ]
@@ -103,6 +103,11 @@ def lib():
                                ctypes.POINTER(_Inject), _vp], ctypes.c_int),
             "ne_plain_gemm_i8": ([_vp, _vp, _vp, _i64, _i64, _i64, _vp], ctypes.c_int),
             "ne_abft_workspace": ([_i64, _i64], _i64),
+            "ne_abft_rc_workspace": ([_i32, _i64, _i64], _i64),
+            "ne_abft_rc_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp, _i64,
+                                    _vp], ctypes.c_int),
+            "ne_abft_rc_check_i8": ([_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp, _i64,
+                                     _vp], ctypes.c_int),
             "ne_abft_gemm_i8": ([_vp, _vp, _vp, _vp, _vp, _i32, _i64, _i64, _i64, _vp, _i64, _vp],
                                 ctypes.c_int),
             "ne_circconv_fused": ([_vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _i64, P, _vp,
@@ -432,6 +437,59 @@ def ne_plain_gemm_i8(A: torch.Tensor, Bt: torch.Tensor, out: torch.Tensor | None
 
 def ne_abft_workspace(n: int, K: int) -> int:
     return int(lib().ne_abft_workspace(n, K))
+
+
+def ne_abft_rc_workspace(M: int, K: int, N: int) -> int:
+    return int(lib().ne_abft_rc_workspace(M, K, N))
+
+
+def _abft_rc(c, Gt, d, gemm, row_flags, col_flags, n_bad, workspace):
+    M, n, K = c.shape
+    N, K2 = Gt.shape
+    if K2 != K:
+        raise ValueError("shape mismatch")
+    if d is None:
+        d = torch.empty((M, n, N), dtype=torch.int32, device=c.device)
+    elif tuple(d.shape) != (M, n, N):
+        raise ValueError("shape mismatch")
+    if row_flags is True:
+        row_flags = torch.empty((M, (n + 31) // 32), dtype=torch.int32, device=c.device)
+    elif row_flags is False:
+        row_flags = None
+    if col_flags is True:
+        col_flags = torch.empty((M, (N + 31) // 32), dtype=torch.int32, device=c.device)
+    elif col_flags is False:
+        col_flags = None
+    if n_bad is None:
+        n_bad = torch.zeros((1,), dtype=torch.int64, device=c.device)
+    if workspace is None:
+        need = ne_abft_rc_workspace(M, K, N)
+        if need <= 0:
+            raise ValueError("invalid sizes")
+        workspace = torch.empty((need // 8 + 2,), dtype=torch.int64, device=c.device)
+    fn = lib().ne_abft_rc_gemm_i8 if gemm else lib().ne_abft_rc_check_i8
+    _ok(fn(_dev(c, "c", torch.int8), _dev(Gt, "Gt", torch.int8), _dev(d, "d", torch.int32),
+           _opt(row_flags, "row_flags", torch.int32), _opt(col_flags, "col_flags", torch.int32),
+           _dev(n_bad, "n_bad", torch.int64), M, n, K, N, *_ws_args(workspace), _stream()),
+        "ne_abft_rc_gemm_i8" if gemm else "ne_abft_rc_check_i8")
+    return d, row_flags, col_flags, n_bad
+
+
+def ne_abft_rc_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None = None,
+                       row_flags: bool | torch.Tensor = True, col_flags: bool | torch.Tensor = True,
+                       n_bad: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Row/column checksum ABFT: c [M, n, K] int8, Gt [N, K] int8 -> (d [M, n, N]
+    int32, row_flags [M, ceil(n/32)], col_flags [M, ceil(N/32)], n_bad).
+    workspace: a tensor of ne_abft_rc_workspace(M, K, N) bytes, or None to
+    allocate one."""
+    return _abft_rc(c, Gt, out, True, row_flags, col_flags, n_bad, workspace)
+
+
+def ne_abft_rc_check_i8(c: torch.Tensor, Gt: torch.Tensor, d: torch.Tensor,
+                        row_flags: bool | torch.Tensor = True, col_flags: bool | torch.Tensor = True,
+                        n_bad: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """The check of ne_abft_rc_gemm_i8 on a given product d [M, n, N] int32."""
+    return _abft_rc(c, Gt, d, False, row_flags, col_flags, n_bad, workspace)[1:]
 
 
 def ne_abft_gemm_i8(c: torch.Tensor, Gt: torch.Tensor, out: torch.Tensor | None = None,

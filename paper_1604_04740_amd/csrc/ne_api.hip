@@ -8,6 +8,7 @@
 
 #include "ne_arith.h"
 #include "ne_internal.h"
+#include "ne_rc.h"
 
 using namespace ne;
 
@@ -44,6 +45,41 @@ hipStream_t hs(ne_stream_t s) { return (hipStream_t)s; }
 bool linconv_sizes_ok(int64_t N, int64_t L)
 {
     return N >= 1 && L >= 1 && L <= kMaxK && N <= ((int64_t)1 << 30) - L + 1;
+}
+
+// Row/column checksum ABFT sizes: 1 <= M <= 4096 subblocks of n x K by
+// K x N, K <= kMaxK, n and N up to 2^20 (exact 64-bit sums, grid limits).
+constexpr int64_t kRcMaxM = 4096, kRcMaxRows = (int64_t)1 << 20;
+
+bool rc_sizes_ok(int64_t M, int64_t n, int64_t K, int64_t N)
+{
+    return M >= 1 && M <= kRcMaxM && n >= 1 && n <= kRcMaxRows && K >= 1 && K <= kMaxK &&
+           N >= 1 && N <= kRcMaxRows;
+}
+
+int rc_entry(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *row_flags,
+             uint32_t *col_flags, unsigned long long *n_bad, int32_t M, int64_t n, int64_t K,
+             int64_t N, void *ws, int64_t ws_bytes, bool gemm, hipStream_t s)
+{
+    if (!rc_sizes_ok(M, n, K, N) || !c || !Gt || !d || !ws)
+        return NE_EINVAL;
+    const int64_t need = ne::rc_workspace_bytes(M, K, N);
+    if (ws_bytes < need)
+        return NE_EINVAL;
+    const int64_t cb = M * n * K, gb = N * K, db = M * n * N * 4;
+    const int64_t rfb = M * ((n + 31) / 32) * 4, cfb = M * ((N + 31) / 32) * 4;
+    const std::pair<const void *, int64_t> bufs[] = {{c, cb},         {Gt, gb},        {d, db},
+                                                     {row_flags, rfb}, {col_flags, cfb}, {n_bad, 8},
+                                                     {ws, need}};
+    // every written buffer (d only when the GEMM runs) apart from the rest
+    for (int i = gemm ? 2 : 3; i < 7; ++i)
+        for (int j = 0; j < 7; ++j)
+            if (i != j && overlap(bufs[i].first, bufs[i].second, bufs[j].first, bufs[j].second))
+                return NE_EALIAS;
+    if ((uintptr_t)d % 4 || (uintptr_t)row_flags % 4 || (uintptr_t)col_flags % 4 ||
+        (uintptr_t)n_bad % 8 || (uintptr_t)ws % 16)
+        return NE_EALIGN;
+    return ne::launch_abft_rc(c, Gt, d, row_flags, col_flags, n_bad, M, n, K, N, ws, gemm, s);
 }
 
 // A linear-convolution workspace: NULL, or at least need bytes, 16-byte
@@ -346,6 +382,31 @@ int ne_plain_gemm_i8(const int8_t *A, const int8_t *Bt, int32_t *C, int64_t R, i
     if ((uintptr_t)C % 4)
         return NE_EALIGN;
     return launch_gemm_plain(A, Bt, C, R, K, N, hs(stream));
+}
+
+int64_t ne_abft_rc_workspace(int32_t M, int64_t K, int64_t N)
+{
+    if (!rc_sizes_ok(M, 1, K, N))
+        return 0;
+    return ne::rc_workspace_bytes(M, K, N);
+}
+
+int ne_abft_rc_gemm_i8(const int8_t *c, const int8_t *Gt, int32_t *d, uint32_t *row_flags,
+                       uint32_t *col_flags, unsigned long long *n_bad, int32_t M, int64_t n,
+                       int64_t K, int64_t N, void *workspace, int64_t workspace_bytes,
+                       ne_stream_t stream)
+{
+    return rc_entry(c, Gt, d, row_flags, col_flags, n_bad, M, n, K, N, workspace, workspace_bytes,
+                    true, hs(stream));
+}
+
+int ne_abft_rc_check_i8(const int8_t *c, const int8_t *Gt, const int32_t *d, uint32_t *row_flags,
+                        uint32_t *col_flags, unsigned long long *n_bad, int32_t M, int64_t n,
+                        int64_t K, int64_t N, void *workspace, int64_t workspace_bytes,
+                        ne_stream_t stream)
+{
+    return rc_entry(c, Gt, const_cast<int32_t *>(d), row_flags, col_flags, n_bad, M, n, K, N,
+                    workspace, workspace_bytes, false, hs(stream));
 }
 
 int64_t ne_abft_workspace(int64_t n, int64_t K)

@@ -78,12 +78,38 @@ __device__ __forceinline__ v4i load_chunk(const int8_t *row_ptr, int64_t k, int6
         return v;
     if (AL) {
         v = *(const v4i *)(row_ptr + k);
+        return v;
+    }
+    // Rows that are not 16-byte aligned: the widest aligned loads the
+    // address allows for a whole chunk (rows of K = 8j or 4j bytes), else
+    // bytes.  Every load of a chunk is issued before any result is used (a
+    // value consumed right after its load would serialise the loads).
+    const int8_t *src = row_ptr + k;
+    const uintptr_t a = (uintptr_t)src;
+    if (k + 16 <= K && (a & 7) == 0) {
+        const uint2 x = *(const uint2 *)src, y = *(const uint2 *)(src + 8);
+        v[0] = (int)x.x;
+        v[1] = (int)x.y;
+        v[2] = (int)y.x;
+        v[3] = (int)y.y;
+    } else if (k + 16 <= K && (a & 3) == 0) {
+        const uint32_t *q = (const uint32_t *)src;
+        const uint32_t x0 = q[0], x1 = q[1], x2 = q[2], x3 = q[3];
+        v[0] = (int)x0;
+        v[1] = (int)x1;
+        v[2] = (int)x2;
+        v[3] = (int)x3;
     } else {
+        // bytes past the end of the row are read from its last byte and
+        // masked off after every load has been issued
+        uint32_t b[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            b[j] = (uint32_t)(uint8_t)src[k + j < K ? j : K - 1 - k];
         uint32_t w[4] = {0, 0, 0, 0};
 #pragma unroll
-        for (int b = 0; b < 16; ++b)
-            if (k + b < K)
-                w[b >> 2] |= (uint32_t)(uint8_t)row_ptr[k + b] << (8 * (b & 3));
+        for (int j = 0; j < 16; ++j)
+            w[j >> 2] |= (k + j < K ? b[j] : 0u) << (8 * (j & 3));
         v[0] = (int)w[0];
         v[1] = (int)w[1];
         v[2] = (int)w[2];

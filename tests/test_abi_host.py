@@ -259,3 +259,29 @@ def test_linconv_workspace(ne):
     assert staged(64 << 20, needs - 1) == ne.NE_EINVAL
     assert staged(1 << 20, needs) == ne.NE_EALIAS             # on top of eps
     assert staged((64 << 20) + 4, needs) == ne.NE_EALIGN
+
+
+def test_abft_rc_arguments(ne):
+    """Workspace size and argument errors of the row/column checksum ABFT
+    (all raised before any launch)."""
+    L_ = ne.lib()
+    assert L_.ne_abft_rc_workspace(4, 2000, 1200) == (5 * 2000 * 4 + 15) // 16 * 16 + 4 * 1200 * 8
+    assert L_.ne_abft_rc_workspace(1, 1, 1) == 16 + 8
+    for args in [(0, 10, 10), (4097, 10, 10), (4, 0, 10), (4, 131072, 10), (4, 10, 0),
+                 (4, 10, (1 << 20) + 1)]:
+        assert L_.ne_abft_rc_workspace(*args) == 0, args
+    c, g, d, ws = (ctypes.c_void_p(a << 24) for a in (1, 2, 3, 4))
+    need = L_.ne_abft_rc_workspace(4, 100, 60)
+    f = lambda c_, d_, ws_, nb=need, rf=None, M=4, n=50, K=100, N=60: L_.ne_abft_rc_gemm_i8(
+        c_, g, d_, rf, None, None, M, n, K, N, ws_, nb, None)
+    assert f(c, d, ws, nb=need - 1) == ne.NE_EINVAL          # workspace too small
+    assert f(c, d, None) == ne.NE_EINVAL                     # workspace required
+    assert f(c, d, ws, M=0) == ne.NE_EINVAL
+    assert f(c, d, ws, n=(1 << 20) + 1) == ne.NE_EINVAL
+    assert f(c, d, ws, K=131072) == ne.NE_EINVAL
+    assert f(c, c, ws) == ne.NE_EALIAS                       # d on top of c
+    assert f(c, d, d) == ne.NE_EALIAS                        # workspace on top of d
+    assert f(c, d, ctypes.c_void_p((4 << 24) + 8)) == ne.NE_EALIGN
+    assert f(c, d, ws, rf=ctypes.c_void_p((5 << 24) + 2)) == ne.NE_EALIGN
+    assert L_.ne_abft_rc_check_i8(c, g, d, ctypes.c_void_p(3 << 24), None, None, 4, 50, 100, 60,
+                                  ws, need, None) == ne.NE_EALIAS   # flags on top of d

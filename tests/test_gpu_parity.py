@@ -147,8 +147,10 @@ def test_permute_scale(ne, orc, M):
 
 # ----------------------------------------------------------- staged GEMM
 
+# K: multiples of 16 (16-byte rows), of 8 (200) and of 4 only (100, 36),
+# and odd (17, 1): every load path of the operand rows
 GEMM_SHAPES = [(3, 64, 64, 64), (4, 100, 200, 300), (3, 33, 48, 45), (5, 7, 17, 129),
-               (4, 1, 1, 1), (8, 70, 96, 200)]
+               (4, 1, 1, 1), (8, 70, 96, 200), (3, 50, 100, 70)]
 
 
 @pytest.mark.parametrize("M,n,K,N", GEMM_SHAPES)
@@ -213,7 +215,8 @@ def test_circconv_any_words(ne, orc, M, N, bits):
 # ------------------------------------------------------------- fused GEMM
 
 FUSED = [(3, 64, 64, 64), (4, 100, 200, 300), (4, 33, 17, 45), (3, 65, 130, 257),
-         (5, 40, 64, 100), (6, 31, 96, 64), (7, 20, 48, 40), (8, 50, 64, 130), (4, 1, 16, 1)]
+         (5, 40, 64, 100), (6, 31, 96, 64), (7, 20, 48, 40), (8, 50, 64, 130), (4, 1, 16, 1),
+         (4, 70, 100, 90), (3, 40, 36, 33)]
 
 
 @pytest.mark.parametrize("M,n,K,N", FUSED)
@@ -278,7 +281,8 @@ def test_fused_gemm_range_and_errors(ne):
 
 # --------------------------------------------------------------- baselines
 
-@pytest.mark.parametrize("R,K,N", [(256, 128, 128), (300, 200, 130), (17, 33, 5), (1024, 512, 384)])
+@pytest.mark.parametrize("R,K,N", [(256, 128, 128), (300, 200, 130), (17, 33, 5), (1024, 512, 384),
+                                   (90, 100, 70), (40, 36, 50)])
 def test_plain_gemm(ne, R, K, N):
     A = ne_synth.uniform_int(1100 + R, 1, (R, K), -128, 128, dtype=np.int8)
     B = ne_synth.uniform_int(1100 + R, 2, (K, N), -128, 128, dtype=np.int8)
@@ -288,7 +292,8 @@ def test_plain_gemm(ne, R, K, N):
 
 
 @pytest.mark.parametrize("M,n,K,N", [(4, 64, 128, 128), (3, 33, 17, 45), (8, 40, 64, 100),
-                                     (4, 70, 272, 300), (1, 5, 16, 7)])
+                                     (4, 70, 272, 300), (1, 5, 16, 7), (3, 30, 100, 40),
+                                     (2, 20, 200, 24)])
 def test_abft_gemm(ne, orc, M, n, K, N):
     c, G = ne_synth.gemm_streams(1200 + M, M, n, K, N, -128, 128)
     c64 = c.astype(np.int64)
