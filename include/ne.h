@@ -586,11 +586,13 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
                   ne_batch_t **plan);
 
 /*
- * Run a planned batch: two persistent launches (one workgroup per compute
- * unit): GEMM tiles, convolution blocks and row copies, then the
- * permutation gathers.  Each workgroup runs the list the plan gave it.  Plain kernels only, so the call can be captured into a HIP graph
- * and replayed.  Runs that share a table must not overlap (the row copies
- * live in the table).
+ * Run a planned batch: up to three launches, in order: the permutations'
+ * row copies, the GEMM tiles and convolution blocks (one persistent
+ * workgroup per compute unit, each running the list the plan gave it),
+ * and the permutation gathers (the two permutation phases split each list
+ * over several workgroups without LDS).  Plain kernels only, so the call
+ * can be captured into a HIP graph and replayed.  Runs that share a table
+ * must not overlap (the row copies live in the table).
  */
 int ne_batch_run(const ne_batch_t *plan, ne_stream_t stream);
 

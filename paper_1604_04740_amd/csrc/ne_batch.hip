@@ -13,13 +13,15 @@
 // tile choices of every (operation, M, size-class) bucket on the device and
 // returns the fastest per bucket.
 //
-// Device side: ne_batch_run launches the persistent kernel twice (grid =
-// one workgroup per CU): phase 0 runs every GEMM tile, convolution block and
-// row copy, phase 1 the permutation gathers that read those rows.  Each
+// Device side: ne_batch_run makes up to three launches.  Phase 0 copies
+// the permutations' inputs into rows and phase 2 runs their gathers, both
+// in a kernel without LDS whose workgroups split each list (many memory
+// accesses in flight per CU); phase 1, the persistent kernel (grid = one
+// workgroup per CU), runs every GEMM tile and convolution block.  Each
 // workgroup runs its own list.  Every loop is bounded by the list bounds in
-// the table, so the grid always drains.  Both
-// launches are plain kernels (no memset nodes), so ne_batch_run can be
-// captured in a HIP graph and replayed.
+// the table, so the grid always drains.  The launches are plain kernels (no
+// memset nodes), so ne_batch_run can be captured in a HIP graph and
+// replayed.
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
@@ -52,15 +54,16 @@ struct DevProblem {
 };
 
 // kind 0: the item of its operation; kind 1: a chunk of a permutation's
-// row copy (first phase; the gathers run in the second).
+// row copy (phase 0; its gathers run in phase 2).
 struct DevItem {
     int32_t problem, a, b, kind;
 };
 
-// Two phases, one launch each: the second (permutation gathers) reads the
-// row copies the first wrote.  Each phase keeps one item list per
-// workgroup: workgroup w of phase p runs items[wg[p][w] .. wg[p][w + 1]),
-// wg an int32 array [2][grid + 1] at wg_off.
+// Three phases, one launch each: row copies, GEMM tiles and convolution
+// blocks, permutation gathers (which read the row copies).  Each phase
+// keeps one item list per workgroup of the persistent grid: list w of
+// phase p is items[wg[p][w] .. wg[p][w + 1]), wg an int32 array
+// [3][grid + 1] at wg_off.
 constexpr int kXcds = 8;
 struct DevHeader {
     int32_t grid, n_problems;
@@ -190,28 +193,37 @@ __device__ __forceinline__ void run_conv(const DevProblem &P, int block, int8_t 
 }
 
 template <int M>
-__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk, bool pack)
+// Positions first + start + tid, stepping by stride, of the chunk.
+__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk, bool pack,
+                                           int64_t start, int64_t stride)
 {
     const int64_t first = (int64_t)chunk * P.chunk;
     const int64_t last = first + P.chunk < P.N ? first + P.chunk : P.N;
     if (pack)
-        perm_pack_range<M, int8_t>((const int8_t *)P.c, P.rows, P.N, P.r, first, last, 0,
-                                   kBatchThreads);
+        perm_pack_range<M, int8_t>((const int8_t *)P.c, P.rows, P.N, P.r, first, last, start,
+                                   stride);
     else
         perm_fused_range<M, int8_t>((const int8_t *)P.c, P.rows, P.perm, P.scale, P.add, P.dhat,
-                                    P.out64, P.flags, P.n_bad, P.N, P.l, P.r, first, last, 0,
-                                    kBatchThreads);
+                                    P.out64, P.flags, P.n_bad, P.N, P.l, P.r, first, last, start,
+                                    stride);
 }
 
-__device__ __forceinline__ void run_perm(const DevProblem &P, int chunk, bool pack)
+template <int M>
+__device__ __forceinline__ void run_perm_m(const DevProblem &P, int chunk, bool pack)
+{
+    run_perm_m<M>(P, chunk, pack, 0, kBatchThreads);
+}
+
+__device__ __forceinline__ void run_perm(const DevProblem &P, int chunk, bool pack,
+                                         int64_t start = 0, int64_t stride = kBatchThreads)
 {
     switch (P.M) {
-    case 3: run_perm_m<3>(P, chunk, pack); return;
-    case 4: run_perm_m<4>(P, chunk, pack); return;
-    case 5: run_perm_m<5>(P, chunk, pack); return;
-    case 6: run_perm_m<6>(P, chunk, pack); return;
-    case 7: run_perm_m<7>(P, chunk, pack); return;
-    case 8: run_perm_m<8>(P, chunk, pack); return;
+    case 3: run_perm_m<3>(P, chunk, pack, start, stride); return;
+    case 4: run_perm_m<4>(P, chunk, pack, start, stride); return;
+    case 5: run_perm_m<5>(P, chunk, pack, start, stride); return;
+    case 6: run_perm_m<6>(P, chunk, pack, start, stride); return;
+    case 7: run_perm_m<7>(P, chunk, pack, start, stride); return;
+    case 8: run_perm_m<8>(P, chunk, pack, start, stride); return;
     default: return;
     }
 }
@@ -248,6 +260,29 @@ __global__ __launch_bounds__(kBatchThreads, 1) void k_batch(const uint8_t *table
     }
 }
 
+// Phases 0 and 2 hold only permutation row copies and gathers, which need
+// many memory accesses in flight rather than LDS: kGatherSplit workgroups
+// without LDS share each list, part q taking the blocks of 256 positions
+// q, q + kGatherSplit, ... of every item (chunks are multiples of 64, so a
+// wavefront's 64 positions stay one aligned run for its flag words).
+constexpr int kGatherSplit = 8;
+__global__ __launch_bounds__(kBatchThreads) void k_batch_gather(const uint8_t *table, int phase)
+{
+    const auto *h = (const DevHeader *)table;
+    const auto *problems = (const DevProblem *)(table + h->problems_off);
+    const auto *items = (const DevItem *)(table + h->items_off);
+    const auto *wg = (const int32_t *)(table + h->wg_off) + phase * (uni(h->grid) + 1);
+    const int list = blockIdx.x / kGatherSplit, part = blockIdx.x % kGatherSplit;
+    const int lo = uni(wg[list]), hi = uni(wg[list + 1]);
+    for (int i = lo; i < hi; ++i) {
+        const DevItem im0 = items[i];
+        const DevItem im = {uni(im0.problem), uni(im0.a), uni(im0.b), uni(im0.kind)};
+        const DevProblem P = uniform(problems[im.problem]);
+        run_perm(P, im.a, im.kind == 1, (int64_t)part * kBatchThreads,
+                 (int64_t)kGatherSplit * kBatchThreads);
+    }
+}
+
 // ------------------------------------------------------------------- host
 
 int size_class(int64_t s)
@@ -267,7 +302,7 @@ int64_t problem_size(const ne_problem_t &p)
 struct BatchPlan {
     void *table;
     int64_t bytes;
-    int n_items[2];
+    int n_items[3];
     int grid; // a multiple of 8: every XCD gets the same number of workgroups
 };
 
@@ -335,9 +370,9 @@ double item_cost(const ne_problem_t &q, int bn, int64_t chunk)
 struct Built {
     std::vector<DevProblem> probs;
     std::vector<DevItem> items; // by phase, then by workgroup
-    std::vector<int32_t> wg;    // [2][grid + 1] list boundaries
+    std::vector<int32_t> wg;    // [3][grid + 1] list boundaries
     int grid = 0;
-    int n_phase[2] = {};
+    int n_phase[3] = {};
     std::vector<int64_t> rows_off; // per problem, offset of its row copy (or -1)
     int64_t rows_bytes = 0;
 };
@@ -350,7 +385,7 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
         double cost;
         int xcd;
     };
-    std::vector<Tmp> tmp[2]; // phase 0, phase 1
+    std::vector<Tmp> tmp[3]; // row copies, GEMM tiles and conv blocks, gathers
     int rr = 0;              // XCD of the next item without locality
     out.probs.resize(count);
     out.rows_off.assign(count, -1);
@@ -399,13 +434,13 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
                 const int gm = std::min(8, d.tiles_m - g0);
                 for (int tn = 0; tn < d.tiles_n; ++tn)
                     for (int tm = g0; tm < g0 + gm; ++tm, ++j)
-                        tmp[0].push_back({{i, tm, tn, 0}, c1, (int)(j * kXcds / ntiles)});
+                        tmp[1].push_back({{i, tm, tn, 0}, c1, (int)(j * kXcds / ntiles)});
             }
         } else if (q.op == NE_OP_CONV) {
             const int blocks = (int)((q.N + kCvBlock - 1) / kCvBlock);
             const double c1 = item_cost(q, 0, 0);
             for (int b = 0; b < blocks; ++b)
-                tmp[0].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
+                tmp[1].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
         } else {
             int64_t chunk = tuning ? tuning->perm_chunk[q.M - 3][cls] : 16384;
             if (chunk < 64)
@@ -418,7 +453,7 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
             out.rows_bytes += (permute_rows_bytes(q.N, q.M, NE_I8) + 255) / 256 * 256;
             for (int b = 0; b < chunks; ++b) {
                 tmp[0].push_back({{i, b, 0, 1}, c1 / 4, rr % kXcds}); // row copy: streaming
-                tmp[1].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
+                tmp[2].push_back({{i, b, 0, 0}, c1, rr++ % kXcds});
             }
         }
     }
@@ -431,8 +466,8 @@ int build(const ne_problem_t *problems, int count, const ne_batch_tuning_t *tuni
     const int per = grid / kXcds;
     out.grid = grid;
     out.items.clear();
-    out.wg.assign(2 * (grid + 1), 0);
-    for (int ph = 0; ph < 2; ++ph) {
+    out.wg.assign(3 * (grid + 1), 0);
+    for (int ph = 0; ph < 3; ++ph) {
         std::stable_sort(tmp[ph].begin(), tmp[ph].end(), by_xcd_cost);
         out.n_phase[ph] = (int)tmp[ph].size();
         std::vector<std::vector<DevItem>> lists(grid);
@@ -506,14 +541,17 @@ int cu_count()
 
 int launch_plan(const BatchPlan &bp, hipStream_t s)
 {
-    if (bp.n_items[0] + bp.n_items[1] == 0)
-        return NE_OK;
-    for (int ph = 0; ph < 2; ++ph)
-        if (bp.n_items[ph] > 0) {
+    for (int ph = 0; ph < 3; ++ph) {
+        if (bp.n_items[ph] == 0)
+            continue;
+        if (ph == 1)
             k_batch<<<bp.grid, kBatchThreads, 0, s>>>((const uint8_t *)bp.table, ph);
-            if (launch_status())
-                return NE_ELAUNCH;
-        }
+        else
+            k_batch_gather<<<bp.grid * kGatherSplit, kBatchThreads, 0, s>>>(
+                (const uint8_t *)bp.table, ph);
+        if (launch_status())
+            return NE_ELAUNCH;
+    }
     return NE_OK;
 }
 
@@ -547,6 +585,7 @@ int ne_batch_plan(const ne_problem_t *problems, int32_t count, const ne_batch_tu
     bp->bytes = *table_needed;
     bp->n_items[0] = b.n_phase[0];
     bp->n_items[1] = b.n_phase[1];
+    bp->n_items[2] = b.n_phase[2];
     bp->grid = grid;
     *plan = (ne_batch_t *)bp;
     return NE_OK;
@@ -564,7 +603,7 @@ int ne_batch_items(const ne_batch_t *plan)
     if (!plan)
         return -1;
     const auto *bp = (const BatchPlan *)plan;
-    return bp->n_items[0] + bp->n_items[1];
+    return bp->n_items[0] + bp->n_items[1] + bp->n_items[2];
 }
 
 void ne_batch_free(ne_batch_t *plan) { free(plan); }
