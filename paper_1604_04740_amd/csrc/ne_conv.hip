@@ -7,6 +7,10 @@
 // 64-bit partial sums, and a second kernel adds them and finishes.
 #include "ne_conv_impl.h"
 
+#ifndef NE_CONV_TARGET_WGS
+#define NE_CONV_TARGET_WGS 256 // about one workgroup per compute unit
+#endif
+
 namespace ne {
 
 ConvSplit conv_split(int64_t N, int M, bool fused)
@@ -15,7 +19,7 @@ ConvSplit conv_split(int64_t N, int M, bool fused)
     const int64_t blocks = (N + kCvBlock - 1) / kCvBlock;
     const int64_t groups = fused ? 1 : (M + kCvMaxSlots - 1) / kCvMaxSlots;
     const int64_t steps = (N + kCvStep - 1) / kCvStep;
-    const int64_t target = 256; // workgroups: about one per compute unit
+    const int64_t target = NE_CONV_TARGET_WGS; // workgroups in total
     int64_t S = (target + blocks * groups - 1) / (blocks * groups);
     if (S > steps)
         S = steps;
